@@ -1,0 +1,209 @@
+"""Seeded synthetic inputs: voxel chunks and camera poses.
+
+This module holds no part of the SVDAG method.  It only produces inputs that
+both the CPU oracle and the GPU library consume:
+
+* dense uint8 chunks (0 = empty, 1..255 = material ID; index
+  ``x + S*(y + S*z)``), from the C generator ``libscenegen.so``;
+* camera poses (position, target, up, vertical FOV, resolution) in float32;
+* tiny random worlds for exhaustive tests (numpy, seeded).
+
+The paper's scenes (voxelised San Miguel, Sponza and the Greenfield Minecraft
+city, Section 4) are not available; the procedural scenes below stand in for
+them.  The workloads are:
+
+``noise64``      one 64^3 chunk of 3D value noise (~30% fill), 256x256 rays.
+``terrain1024``  one 1024^3 terrain chunk with caves, 1920x1080 rays.
+``map512``       16x16 chunks of 512^3 terrain + box buildings, 4 LODs,
+                 2560x1440 rays (the 1440p throughput workload).
+``map1024``      32x32 chunks of 1024^3, 4 LODs.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+KINDS = {"noise64": 0, "terrain1024": 1, "map512": 2, "map1024": 3, "custom": 4}
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, "libscenegen.so")
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the generator with gcc (host code only)."""
+    import subprocess
+
+    src = os.path.join(_HERE, "scenegen.c")
+    out = lib_path()
+    cmd = ["gcc", "-O2", "-Wall", "-fPIC", "-shared", "-fvisibility=hidden",
+           "-o", out + ".tmp", src, "-lm", "-lpthread"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        p = lib_path()
+        if not os.path.exists(p):
+            raise RuntimeError(f"{p} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(p)
+        L.sg_world_new.restype = ctypes.c_void_p
+        L.sg_world_new.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
+                                   ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
+        L.sg_world_free.argtypes = [ctypes.c_void_p]
+        L.sg_world_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
+                                    ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_int)]
+        L.sg_height.restype = ctypes.c_int64
+        L.sg_height.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64]
+        L.sg_gen_chunk.restype = ctypes.c_int
+        L.sg_gen_chunk.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                   ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int]
+        L.sg_splitmix64.restype = ctypes.c_uint64
+        L.sg_splitmix64.argtypes = [ctypes.c_uint64]
+        _LIB = L
+    return _LIB
+
+
+def splitmix64(x: int) -> int:
+    return int(_lib().sg_splitmix64(ctypes.c_uint64(x & 0xFFFFFFFFFFFFFFFF)))
+
+
+@dataclass
+class Camera:
+    """Pinhole camera in voxel units; +z is up, vertical FOV in degrees."""
+    pos: tuple
+    target: tuple
+    up: tuple
+    vfov_deg: float
+    width: int
+    height: int
+
+    def as_f32(self):
+        f = lambda v: tuple(float(np.float32(x)) for x in v)
+        return Camera(f(self.pos), f(self.target), f(self.up),
+                      float(np.float32(self.vfov_deg)), int(self.width), int(self.height))
+
+
+class SceneWorld:
+    """A seeded procedural world, generated one chunk at a time."""
+
+    def __init__(self, kind: str, seed: int, chunk_log2: int = 0, grid=(1, 1, 1)):
+        L = _lib()
+        self.kind = kind
+        self.seed = int(seed)
+        h = L.sg_world_new(KINDS[kind], ctypes.c_uint64(self.seed), chunk_log2, *grid)
+        if not h:
+            raise ValueError(f"bad scene kind {kind!r}")
+        self._h = h
+        cl = ctypes.c_uint32()
+        g = (ctypes.c_uint32 * 3)()
+        nb = ctypes.c_int()
+        L.sg_world_info(h, ctypes.byref(cl), g, ctypes.byref(nb))
+        self.chunk_log2 = cl.value
+        self.grid = (g[0], g[1], g[2])
+        self.nbox = nb.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib().sg_world_free(h)
+            self._h = None
+
+    @property
+    def S(self) -> int:
+        return 1 << self.chunk_log2
+
+    @property
+    def extent(self):
+        return tuple(g * self.S for g in self.grid)
+
+    def chunks(self):
+        gx, gy, gz = self.grid
+        for cz in range(gz):
+            for cy in range(gy):
+                for cx in range(gx):
+                    yield (cx, cy, cz)
+
+    def chunk(self, c, out: np.ndarray | None = None, threads: int = 1) -> np.ndarray:
+        S = self.S
+        if out is None:
+            out = np.empty(S * S * S, dtype=np.uint8)
+        assert out.dtype == np.uint8 and out.size == S ** 3 and out.flags.c_contiguous
+        rc = _lib().sg_gen_chunk(self._h, c[0], c[1], c[2], out.ctypes.data, int(threads))
+        if rc != 0:
+            raise ValueError(f"chunk {c} out of range")
+        return out
+
+    def height(self, x: int, y: int) -> int:
+        return int(_lib().sg_height(self._h, int(x), int(y)))
+
+    # -- camera poses ------------------------------------------------------
+    def views(self, n: int, seed: int, width: int | None = None, height: int | None = None):
+        """Seeded camera poses for this workload (float32-representable)."""
+        rng = np.random.default_rng([self.seed, seed, 0xC0FFEE])
+        cams = []
+        X, Y, Z = self.extent
+        for _ in range(n):
+            if self.kind == "noise64":
+                u = rng.normal(size=3)
+                u /= np.linalg.norm(u)
+                c = np.array([X / 2, Y / 2, Z / 2])
+                pos = c + 96.0 * u
+                cam = Camera(tuple(pos), tuple(c), (0.0, 0.0, 1.0), 60.0,
+                             width or 256, height or 256)
+            else:
+                if self.kind == "terrain1024":
+                    margin, pitch_lo, pitch_hi, W, H = 64, -30.0, 0.0, 1920, 1080
+                elif self.kind == "custom":
+                    margin, pitch_lo, pitch_hi, W, H = 2, -30.0, 10.0, 64, 48
+                else:
+                    margin, pitch_lo, pitch_hi, W, H = 256, -20.0, 5.0, 2560, 1440
+                x = rng.uniform(margin, X - margin)
+                y = rng.uniform(margin, Y - margin)
+                hz = self.height(int(x), int(y))
+                z = min(hz + 50.0, Z - 0.5) if self.kind != "custom" else min(hz + 3.5, Z - 0.5)
+                yaw = rng.uniform(0.0, 2.0 * math.pi)
+                if self.kind == "custom":
+                    # small test worlds: look roughly towards the middle
+                    yaw = math.atan2(Y / 2 - y, X / 2 - x) + rng.uniform(-0.6, 0.6)
+                    pitch_lo, pitch_hi = -35.0, -5.0
+                pitch = math.radians(rng.uniform(pitch_lo, pitch_hi))
+                d = np.array([math.cos(pitch) * math.cos(yaw),
+                              math.cos(pitch) * math.sin(yaw), math.sin(pitch)])
+                pos = np.array([x, y, z])
+                cam = Camera(tuple(pos), tuple(pos + 100.0 * d), (0.0, 0.0, 1.0), 60.0,
+                             width or W, height or H)
+            cams.append(cam.as_f32())
+        return cams
+
+
+# -- tiny random worlds (tests) -------------------------------------------
+
+def random_grid(rng: np.random.Generator, R: int, fill: float, nmat: int = 15,
+                structured: bool = True) -> np.ndarray:
+    """Random R^3 uint8 grid (index x + R*(y + R*z)).
+
+    With ``structured`` the occupancy is drawn per 2^3 block first and then
+    per voxel, so that empty and full sub-cubes of several sizes occur.
+    """
+    if structured and R >= 4:
+        blk = rng.random((R // 2, R // 2, R // 2)) < min(1.0, 2.5 * fill)
+        occ = np.repeat(np.repeat(np.repeat(blk, 2, 0), 2, 1), 2, 2)
+        occ &= rng.random((R, R, R)) < min(1.0, fill / max(1e-9, min(1.0, 2.5 * fill)) * 1.0)
+    else:
+        occ = rng.random((R, R, R)) < fill
+    mat = rng.integers(1, nmat + 1, size=(R, R, R), dtype=np.uint8)
+    g = np.where(occ, mat, 0).astype(np.uint8)  # axes (z, y, x) after flatten order below
+    return np.ascontiguousarray(g).reshape(-1)
