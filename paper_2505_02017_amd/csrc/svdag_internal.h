@@ -1,0 +1,105 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// libsvdag.  Nothing here is part of the public ABI (include/svdag.h).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "svdag.h"
+
+namespace svd {
+
+// Device descriptor of one (chunk, LOD) DAG: 64 bytes, one per (chunk, LOD)
+// slot in the world's table.
+//
+// Device node layout (derived from the canonical node format of Section
+// 3.2): a node with k children is k consecutive u32 "child words",
+// child word = (mask of the child << 24) | pointer, in ascending octant.
+// The pointer of an internal child is the child's word offset; for the
+// children of a level-3 node it indexes the u64 leaf bitmaps.  Keeping the
+// child's mask in its parent makes every descent one 4-byte load.  A parallel
+// u32 array `pre` holds, at the same offsets, the solid count of the earlier
+// siblings (the DFS prefix of Section 3.3), read only once per hit.
+struct alignas(64) DevDag {
+  uint64_t nodes;      // device address: u32 child words
+  uint64_t leaves;     // device address: u64 leaf bitmaps
+  uint64_t pre;        // device address: u32 prefix counts, parallel to nodes
+  uint64_t rle_start;  // device address: u32 run starts (DFS index)
+  uint64_t rle_mat;    // device address: u8 run materials
+  uint32_t rle_n;      // number of runs
+  uint32_t root;       // child word of the root: (root mask << 24) | 0
+  uint32_t solid;      // solid cells at this LOD (0 = empty)
+  uint16_t lo[3];      // tight box of solid cells, LOD cells, inclusive
+  uint16_t hi[3];
+};
+static_assert(sizeof(DevDag) == 64, "DevDag must stay 64 bytes");
+
+constexpr uint32_t kPtrBits = 24;
+constexpr uint32_t kPtrMask = (1u << kPtrBits) - 1;
+
+// Per-chunk entry of the per-view table written by the chunk stage.
+constexpr uint32_t kViewLodMask = 3u;
+constexpr uint32_t kViewCulled = 4u;
+constexpr uint32_t kViewEmpty = 8u;
+
+struct LodData {
+  uint32_t R = 0;
+  uint32_t root_level = 0;
+  // canonical form (paper's node format)
+  std::vector<uint32_t> words;
+  std::vector<uint64_t> leaves;
+  std::vector<uint32_t> rle_start;
+  std::vector<uint8_t> rle_mat;
+  uint32_t n_solid = 0;
+  uint32_t level_nodes[16] = {};
+  uint16_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  // device image sections, byte offsets inside the blob's image
+  uint64_t off_nodes = 0, off_pre = 0, off_leaves = 0, off_rle_start = 0, off_rle_mat = 0;
+  uint64_t off_begin = 0, off_end = 0;
+  uint32_t dev_words = 0;
+  uint32_t root_word = 0;
+};
+
+// Kernel parameters of one traced view.
+struct TraceParams {
+  int64_t O[3];
+  int64_t A[3], BX[3], BY[3];
+  uint32_t W, H;
+  uint32_t grid[3];
+  uint32_t chunk_log2;
+  uint32_t tiles_x;       // 16x16-pixel blocks per row
+  uint32_t nblocks;
+  const uint32_t* view;   // per-chunk view entry
+  const DevDag* desc;     // [chunk * 4 + lod]
+  svd_hit* out;
+};
+
+struct StageParams {
+  int64_t O[3];
+  int64_t n[4][3];        // cull planes through O (inward normals); zero = none
+  uint32_t grid[3];
+  uint32_t chunk_log2;
+  uint32_t lod_count;
+  uint32_t thr[3];
+  uint32_t cull;          // 0 = keep every non-empty chunk
+  uint32_t nchunks;
+  const DevDag* desc;
+  uint32_t* view;
+};
+
+// kernels.hip
+int launch_chunk_stage(const StageParams& p, void* stream);
+int launch_trace(const TraceParams& p, void* stream);
+int launch_set_desc(DevDag* dst, const DevDag* src4, uint32_t n, void* stream);
+
+}  // namespace svd
+
+struct svd_blob {
+  uint32_t chunk_log2 = 0;
+  uint32_t lod_count = 0;
+  std::vector<svd::LodData> lod;
+  std::vector<uint8_t> image;  // device image of every LOD (256-byte sections)
+};
+
+// Thread-local error message; returns `code` for convenient `return fail(...)`.
+int svd_fail(int code, const char* fmt, ...);

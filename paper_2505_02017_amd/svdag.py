@@ -1,0 +1,331 @@
+"""ctypes binding of libsvdag (include/svdag.h).
+
+Argument marshalling only: every step of the build runs in the library's
+C++ and every step of a traced view runs in its HIP kernels.  PyTorch is used
+for device memory (pool and output tensors) and streams.  Importing this
+module fails loudly if ``libsvdag.so`` has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsvdag.so")
+
+SVD_OK = 0
+SVD_EINVAL = -1
+SVD_ENOMEM = -2
+SVD_EDEVICE = -3
+SVD_EFORMAT = -4
+SVD_ERANGE = -5
+SVD_ENOTFOUND = -6
+SVD_NO_CULL = 1
+FAULT_CHUNK = 0xFFFFFFFE  # written by the trace if its iteration guard fires
+
+_NAMES = {SVD_EINVAL: "EINVAL", SVD_ENOMEM: "ENOMEM", SVD_EDEVICE: "EDEVICE",
+          SVD_EFORMAT: "EFORMAT", SVD_ERANGE: "ERANGE", SVD_ENOTFOUND: "ENOTFOUND"}
+
+EXPORTS = [
+    "svd_last_error", "svd_chunk_build", "svd_blob_to_bytes", "svd_blob_from_bytes",
+    "svd_blob_free", "svd_free", "svd_blob_stats_get", "svd_blob_canonical",
+    "svd_world_create", "svd_world_destroy", "svd_world_pool_used", "svd_chunk_upload",
+    "svd_chunk_evict", "svd_camera_frame", "svd_trace_view", "svd_trace_frame",
+    "svd_view_table",
+]
+
+
+class SvdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class svd_world_desc(ctypes.Structure):
+    _fields_ = [("chunk_log2", ctypes.c_uint32), ("grid", ctypes.c_uint32 * 3),
+                ("lod_count", ctypes.c_uint32), ("lod_threshold", ctypes.c_uint32 * 3)]
+
+
+class svd_camera(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_float * 3), ("target", ctypes.c_float * 3),
+                ("up", ctypes.c_float * 3), ("vfov_deg", ctypes.c_float),
+                ("width", ctypes.c_uint32), ("height", ctypes.c_uint32)]
+
+
+class svd_ray_frame(ctypes.Structure):
+    _fields_ = [("O", ctypes.c_int64 * 3), ("A", ctypes.c_int64 * 3),
+                ("BX", ctypes.c_int64 * 3), ("BY", ctypes.c_int64 * 3),
+                ("G", ctypes.c_int32), ("width", ctypes.c_uint32), ("height", ctypes.c_uint32)]
+
+
+class svd_blob_stats(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_uint32), ("n_words", ctypes.c_uint32),
+                ("n_leaves", ctypes.c_uint32), ("n_rle", ctypes.c_uint32),
+                ("n_solid", ctypes.c_uint32), ("level_nodes", ctypes.c_uint32 * 16),
+                ("aabb_lo", ctypes.c_uint16 * 3), ("aabb_hi", ctypes.c_uint16 * 3),
+                ("device_bytes", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u32, i32, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_size_t
+        L.svd_last_error.restype = ctypes.c_char_p
+        L.svd_last_error.argtypes = []
+        L.svd_chunk_build.argtypes = [vp, u32, u32, ctypes.POINTER(vp)]
+        L.svd_blob_to_bytes.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(sz)]
+        L.svd_blob_from_bytes.argtypes = [vp, sz, ctypes.POINTER(vp)]
+        L.svd_blob_free.argtypes = [vp]
+        L.svd_blob_free.restype = None
+        L.svd_free.argtypes = [vp]
+        L.svd_free.restype = None
+        L.svd_blob_stats_get.argtypes = [vp, u32, ctypes.POINTER(svd_blob_stats)]
+        L.svd_blob_canonical.argtypes = [vp, u32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                         ctypes.POINTER(vp), ctypes.POINTER(vp)]
+        L.svd_world_create.argtypes = [ctypes.POINTER(svd_world_desc), vp, sz, ctypes.POINTER(vp)]
+        L.svd_world_destroy.argtypes = [vp]
+        L.svd_world_destroy.restype = None
+        L.svd_world_pool_used.argtypes = [vp, ctypes.POINTER(sz)]
+        L.svd_chunk_upload.argtypes = [vp, ctypes.POINTER(u32), vp, vp]
+        L.svd_chunk_evict.argtypes = [vp, ctypes.POINTER(u32)]
+        L.svd_camera_frame.argtypes = [ctypes.POINTER(svd_camera), ctypes.POINTER(svd_ray_frame)]
+        L.svd_trace_view.argtypes = [vp, ctypes.POINTER(svd_camera), vp, u32, vp]
+        L.svd_trace_frame.argtypes = [vp, ctypes.POINTER(svd_ray_frame), vp, u32, vp]
+        L.svd_view_table.argtypes = [vp, ctypes.POINTER(u32), u32, vp]
+        for n in EXPORTS:
+            if n not in ("svd_last_error", "svd_blob_free", "svd_free", "svd_world_destroy"):
+                getattr(L, n).restype = i32
+        _lib = L
+    return _lib
+
+
+def svd_last_error() -> str:
+    return lib().svd_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != SVD_OK:
+        raise SvdError(rc, svd_last_error())
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    if hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    return ctypes.c_void_p(int(stream))
+
+
+# ------------------------------------------------------------------ blobs
+
+class Blob:
+    """Host-side built chunk (all LODs); frees itself."""
+
+    def __init__(self, ptr: int):
+        self._p = ctypes.c_void_p(ptr)
+
+    def __del__(self):
+        if getattr(self, "_p", None) and self._p.value:
+            lib().svd_blob_free(self._p)
+            self._p = None
+
+    @property
+    def ptr(self):
+        return self._p
+
+
+def svd_chunk_build(dense: np.ndarray, chunk_log2: int, lod_count: int) -> Blob:
+    d = np.ascontiguousarray(dense, dtype=np.uint8).reshape(-1)
+    if d.size != (1 << (3 * chunk_log2)):
+        raise SvdError(SVD_EINVAL, "dense grid has the wrong size")
+    out = ctypes.c_void_p()
+    _check(lib().svd_chunk_build(d.ctypes.data, chunk_log2, lod_count, ctypes.byref(out)))
+    return Blob(out.value)
+
+
+def svd_blob_to_bytes(b: Blob) -> bytes:
+    p = ctypes.c_void_p()
+    n = ctypes.c_size_t()
+    _check(lib().svd_blob_to_bytes(b.ptr, ctypes.byref(p), ctypes.byref(n)))
+    try:
+        return ctypes.string_at(p, n.value)
+    finally:
+        lib().svd_free(p)
+
+
+def svd_blob_from_bytes(data: bytes) -> Blob:
+    buf = ctypes.create_string_buffer(bytes(data), len(data))
+    out = ctypes.c_void_p()
+    _check(lib().svd_blob_from_bytes(buf, len(data), ctypes.byref(out)))
+    return Blob(out.value)
+
+
+def svd_blob_stats_get(b: Blob, lod: int) -> dict:
+    s = svd_blob_stats()
+    _check(lib().svd_blob_stats_get(b.ptr, lod, ctypes.byref(s)))
+    return dict(R=s.R, n_words=s.n_words, n_leaves=s.n_leaves, n_rle=s.n_rle, n_solid=s.n_solid,
+                level_nodes=list(s.level_nodes), aabb_lo=list(s.aabb_lo), aabb_hi=list(s.aabb_hi),
+                device_bytes=int(s.device_bytes))
+
+
+def svd_blob_canonical(b: Blob, lod: int):
+    """Copies of the canonical arrays (words, leaves, rle_start, rle_mat)."""
+    st = svd_blob_stats_get(b, lod)
+    w, l, rs, rm = (ctypes.c_void_p() for _ in range(4))
+    _check(lib().svd_blob_canonical(b.ptr, lod, ctypes.byref(w), ctypes.byref(l),
+                                    ctypes.byref(rs), ctypes.byref(rm)))
+
+    def arr(p, n, t):
+        if n == 0:
+            return np.zeros(0, t)
+        return np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(np.ctypeslib.as_ctypes_type(t))),
+                                     (n,)).copy()
+    return (arr(w, st["n_words"], np.uint32), arr(l, st["n_leaves"], np.uint64),
+            arr(rs, st["n_rle"], np.uint32), arr(rm, st["n_rle"], np.uint8))
+
+
+# ------------------------------------------------------------------ world
+
+def make_desc(chunk_log2: int, grid, lod_count: int, thresholds=(256, 1024, 4096)) -> svd_world_desc:
+    d = svd_world_desc()
+    d.chunk_log2 = chunk_log2
+    d.grid[:] = [int(g) for g in grid]
+    d.lod_count = lod_count
+    t = list(thresholds) + [0] * (3 - len(thresholds))
+    d.lod_threshold[:] = [int(x) for x in t[:3]]
+    return d
+
+
+def table_bytes(grid) -> int:
+    n = int(grid[0]) * int(grid[1]) * int(grid[2])
+    return n * 4 * 64 + (n * 4 + 255) // 256 * 256
+
+
+class World:
+    """A device world over a caller-owned pool tensor (torch uint8, on a GPU)."""
+
+    def __init__(self, ptr: int, pool, desc: svd_world_desc):
+        self._p = ctypes.c_void_p(ptr)
+        self.pool = pool          # keeps the device memory alive
+        self.desc = desc
+        self.grid = tuple(desc.grid)
+        self.nchunks = self.grid[0] * self.grid[1] * self.grid[2]
+        self._blobs = {}          # uploaded blobs stay alive until replaced or evicted
+
+    @property
+    def ptr(self):
+        return self._p
+
+    def __del__(self):
+        if getattr(self, "_p", None) and self._p.value:
+            lib().svd_world_destroy(self._p)
+            self._p = None
+
+
+def svd_world_create(desc: svd_world_desc, pool) -> World:
+    assert pool.dtype.itemsize == 1 and pool.is_contiguous()
+    out = ctypes.c_void_p()
+    _check(lib().svd_world_create(ctypes.byref(desc), ctypes.c_void_p(pool.data_ptr()),
+                                  pool.numel(), ctypes.byref(out)))
+    return World(out.value, pool, desc)
+
+
+def svd_world_destroy(w: World):
+    if w._p and w._p.value:
+        lib().svd_world_destroy(w._p)
+        w._p = None
+
+
+def svd_world_pool_used(w: World) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().svd_world_pool_used(w.ptr, ctypes.byref(n)))
+    return n.value
+
+
+def _c3(c):
+    return (ctypes.c_uint32 * 3)(*[int(v) for v in c])
+
+
+def svd_chunk_upload(w: World, c, b: Blob, stream=None):
+    _check(lib().svd_chunk_upload(w.ptr, _c3(c), b.ptr, _stream_ptr(stream)))
+    w._blobs[tuple(int(v) for v in c)] = b
+
+
+def svd_chunk_evict(w: World, c):
+    _check(lib().svd_chunk_evict(w.ptr, _c3(c)))
+    w._blobs.pop(tuple(int(v) for v in c), None)
+
+
+def to_camera(cam) -> svd_camera:
+    c = svd_camera()
+    c.pos[:] = [float(v) for v in cam.pos]
+    c.target[:] = [float(v) for v in cam.target]
+    c.up[:] = [float(v) for v in cam.up]
+    c.vfov_deg = float(cam.vfov_deg)
+    c.width = int(cam.width)
+    c.height = int(cam.height)
+    return c
+
+
+def svd_camera_frame(cam) -> svd_ray_frame:
+    f = svd_ray_frame()
+    _check(lib().svd_camera_frame(ctypes.byref(to_camera(cam)), ctypes.byref(f)))
+    return f
+
+
+def make_frame(O, A, BX, BY, width, height, G=0) -> svd_ray_frame:
+    f = svd_ray_frame()
+    f.O[:] = [int(v) for v in O]
+    f.A[:] = [int(v) for v in A]
+    f.BX[:] = [int(v) for v in BX]
+    f.BY[:] = [int(v) for v in BY]
+    f.G = G
+    f.width = width
+    f.height = height
+    return f
+
+
+def _out_ptr(out, n: int):
+    assert out.is_cuda and out.is_contiguous() and out.numel() * out.element_size() >= 16 * n
+    return ctypes.c_void_p(out.data_ptr())
+
+
+def svd_trace_view(w: World, cam, out, flags: int = 0, stream=None):
+    c = cam if isinstance(cam, svd_camera) else to_camera(cam)
+    _check(lib().svd_trace_view(w.ptr, ctypes.byref(c), _out_ptr(out, c.width * c.height),
+                                flags, _stream_ptr(stream)))
+
+
+def svd_trace_frame(w: World, frame: svd_ray_frame, out, flags: int = 0, stream=None):
+    _check(lib().svd_trace_frame(w.ptr, ctypes.byref(frame), _out_ptr(out, frame.width * frame.height),
+                                 flags, _stream_ptr(stream)))
+
+
+def svd_view_table(w: World, stream=None) -> np.ndarray:
+    out = np.zeros(w.nchunks, np.uint32)
+    _check(lib().svd_view_table(w.ptr, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                w.nchunks, _stream_ptr(stream)))
+    return out
+
+
+# ------------------------------------------------------------------ records
+
+def decode_hits(raw: np.ndarray) -> dict:
+    """Fields of svd_hit records (array of uint32 with 4 words per pixel)."""
+    r = np.ascontiguousarray(raw).view(np.uint32).reshape(-1, 4)
+    xy, zf, chunk = r[:, 0], r[:, 1], r[:, 3]
+    return dict(
+        x=(xy & 0xFFFF).astype(np.int32), y=(xy >> 16).astype(np.int32),
+        z=(zf & 0xFFFF).astype(np.int32), lod=((zf >> 16) & 0xF).astype(np.int32),
+        face=((zf >> 20) & 0x7).astype(np.int32), hit=((zf >> 23) & 1).astype(np.int32),
+        material=(zf >> 24).astype(np.int32), t=r[:, 2].view(np.float32), chunk=chunk,
+    )

@@ -1,0 +1,147 @@
+"""Host-side checks of libsvdag (no GPU needed): exported symbols, the
+host builder against the oracle, blob serialisation and validation, and the
+camera frame against the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2505_02017_amd import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _svdag():
+    from paper_2505_02017_amd import svdag
+    if not os.path.exists(svdag.LIB_PATH):
+        from paper_2505_02017_amd import build
+        build.build_lib()
+    return svdag
+
+
+def test_exports_match_header():
+    svdag = _svdag()
+    hdr = open(os.path.join(ROOT, "include", "svdag.h")).read()
+    declared = set(re.findall(r"\b(svd_[a-z_]+)\s*\(", hdr))
+    declared -= {"svd_hit"}
+    L = ctypes.CDLL(svdag.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    assert declared == set(svdag.EXPORTS)
+
+
+def _compare_blob(svdag, g, R, lod_count):
+    b = svdag.svd_chunk_build(g, R.bit_length() - 1, lod_count)
+    pyr = oracle.pyramid(g, R, lod_count)
+    for k in range(lod_count):
+        d = oracle.Dag(pyr[k], R >> k)
+        w, l, rs, rm = svdag.svd_blob_canonical(b, k)
+        assert np.array_equal(w, d.words), k
+        assert np.array_equal(l, d.leaves), k
+        assert np.array_equal(rs, d.rle_start), k
+        assert np.array_equal(rm, d.rle_mat), k
+        st = svdag.svd_blob_stats_get(b, k)
+        assert st["n_solid"] == d.n_solid
+        assert st["level_nodes"][2:d.R.bit_length()] == d.level_nodes[2:d.R.bit_length()]
+        if d.n_solid:
+            G = pyr[k].reshape(R >> k, R >> k, R >> k)
+            zs, ys, xs = np.nonzero(G)
+            assert st["aabb_lo"] == [xs.min(), ys.min(), zs.min()]
+            assert st["aabb_hi"] == [xs.max(), ys.max(), zs.max()]
+    return b
+
+
+@pytest.mark.parametrize("R,fill,lods", [(8, 0.3, 1), (16, 0.02, 2), (32, 0.2, 3), (32, 0.9, 3),
+                                          (64, 0.05, 4)])
+def test_builder_matches_oracle_random(R, fill, lods):
+    svdag = _svdag()
+    rng = np.random.default_rng(R * 100 + int(fill * 100))
+    for structured in (True, False):
+        _compare_blob(svdag, scenes.random_grid(rng, R, fill, structured=structured), R, lods)
+
+
+def test_builder_matches_oracle_generated():
+    svdag = _svdag()
+    _compare_blob(svdag, scenes.SceneWorld("noise64", 3).chunk((0, 0, 0)), 64, 4)
+    sw = scenes.SceneWorld("custom", 9, chunk_log2=7, grid=(2, 2, 1))
+    _compare_blob(svdag, sw.chunk((1, 0, 0)), 128, 4)
+
+
+def test_builder_empty_and_full():
+    svdag = _svdag()
+    b = _compare_blob(svdag, np.zeros(32 ** 3, np.uint8), 32, 3)
+    assert svdag.svd_blob_stats_get(b, 0)["n_words"] == 0
+    _compare_blob(svdag, np.full(32 ** 3, 200, np.uint8), 32, 3)
+
+
+def test_blob_bytes_roundtrip_and_rejects():
+    svdag = _svdag()
+    rng = np.random.default_rng(7)
+    g = scenes.random_grid(rng, 32, 0.2)
+    b = svdag.svd_chunk_build(g, 5, 3)
+    data = svdag.svd_blob_to_bytes(b)
+    b2 = svdag.svd_blob_from_bytes(data)
+    assert svdag.svd_blob_to_bytes(b2) == data
+    for k in range(3):
+        assert svdag.svd_blob_stats_get(b, k) == svdag.svd_blob_stats_get(b2, k)
+    # truncations and trailing bytes are rejected
+    for n in (0, 3, 16, len(data) // 2, len(data) - 1):
+        with pytest.raises(svdag.SvdError) as e:
+            svdag.svd_blob_from_bytes(data[:n])
+        assert e.value.code == svdag.SVD_EFORMAT
+    with pytest.raises(svdag.SvdError):
+        svdag.svd_blob_from_bytes(data + b"\0" * 8)
+    # single-word corruptions: rejected, or accepted only if still consistent
+    arr = np.frombuffer(data, np.uint32).copy()
+    for _ in range(300):
+        bad = arr.copy()
+        i = int(rng.integers(4, bad.size))
+        bad[i] ^= np.uint32(1 << int(rng.integers(0, 32)))
+        try:
+            b3 = svdag.svd_blob_from_bytes(bad.tobytes())
+        except svdag.SvdError as e:
+            assert e.code in (svdag.SVD_EFORMAT, svdag.SVD_ERANGE)
+            continue
+        # accepted: it must re-serialise to itself (a consistent blob)
+        assert svdag.svd_blob_to_bytes(b3) == bad.tobytes()
+
+
+def test_build_rejects_bad_arguments():
+    svdag = _svdag()
+    with pytest.raises(svdag.SvdError):
+        svdag.svd_chunk_build(np.zeros(8 ** 3, np.uint8), 3, 2)   # coarsest grid < 8^3
+    with pytest.raises(svdag.SvdError):
+        svdag.svd_chunk_build(np.zeros(4 ** 3, np.uint8), 2, 1)   # chunk too small
+
+
+def test_camera_frame_matches_oracle():
+    svdag = _svdag()
+    rng = np.random.default_rng(12)
+    cams = []
+    for kind in ("noise64", "custom"):
+        sw = scenes.SceneWorld(kind, 4, chunk_log2=6, grid=(3, 3, 1))
+        cams += sw.views(20, 2)
+    for _ in range(200):
+        pos = rng.uniform(-30000, 60000, 3)
+        cams.append(scenes.Camera(tuple(pos), tuple(pos + rng.normal(size=3) * rng.uniform(0.01, 1e4)),
+                                  tuple(rng.normal(size=3)), float(rng.uniform(0.5, 170)),
+                                  int(rng.integers(1, 5000)), int(rng.integers(1, 3000))).as_f32())
+    n_ok = 0
+    for cam in cams:
+        try:
+            fo = oracle.camera_frame(cam)
+        except ValueError:
+            with pytest.raises(svdag.SvdError):
+                svdag.svd_camera_frame(cam)
+            continue
+        fl = svdag.svd_camera_frame(cam)
+        assert list(fl.O) == fo.O.tolist()
+        assert list(fl.A) == fo.A.tolist()
+        assert list(fl.BX) == fo.BX.tolist()
+        assert list(fl.BY) == fo.BY.tolist()
+        assert fl.G == fo.G
+        n_ok += 1
+    assert n_ok > 150
