@@ -1,0 +1,275 @@
+#!/usr/bin/env python3
+"""Throughput of chunked-SVDAG primary-ray traversal on one MI355X.
+
+One step = one view through the whole hot path: the chunk stage (LOD pick
+and frustum cull per chunk) and the per-pixel trace (chunk walk, DAG
+traversal, material resolve, record write), with every chunk DAG already
+resident in HBM.  Steps cycle over 10 seeded camera poses.
+
+Prints one JSON line (rank 0).  Besides the throughput it reports:
+  roofline      for the trace kernel: algorithmic bytes per launch (mean
+                bytes per ray from the oracle's visit counts x rays) over the
+                kernel's mean duration (HIP events on its stream), against
+                the 8 TB/s HBM peak;
+  cpu_baseline  the CPU oracle timed on a bounded sample of the same views.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    # name: (scene kind, lod_count, thresholds, description)
+    "map512": ("map512", 4, (256, 1024, 4096),
+               "map512: 16x16x1 chunks of 512^3 (8192x8192x512) terrain+caves+boxes, 4 LODs, "
+               "frustum culling, 2560x1440 rays, 10 seeded views"),
+    "terrain1024": ("terrain1024", 1, (256, 1024, 4096),
+                    "terrain1024: one 1024^3 terrain chunk with caves, 1920x1080 rays, 10 seeded views"),
+    "noise64": ("noise64", 1, (256, 1024, 4096),
+                "noise64: one 64^3 value-noise chunk (~30% fill), 256x256 rays, 10 seeded views"),
+}
+HBM_PEAK_GBS = 8000.0
+METRIC = "primary rays/s (Grays/s) of SVDAG traversal at 1440p; p50/p99 view latency under load"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def bytes_per_ray(counts, hits, lods, chunk_log2, n_rle):
+    """Algorithmic bytes of the trace kernel for each ray:
+    4 B view entry per chunk visited; 20 B per chunk DAG entered (node and
+    leaf array addresses, root word); 4 B child word per internal node
+    entered; 12 B (child word + bitmap) per leaf entered; at a hit 28 B
+    (prefix and run array addresses, run count), 4 B per internal level
+    (DFS prefix), 4 B per run search step and 1 B material; the 16 B record."""
+    b = (4.0 * counts["chunk_visits"] + 20.0 * counts["chunk_entries"] +
+         4.0 * counts["node_cubes"] + 12.0 * counts["leaf_cubes"] + 16.0)
+    h = hits["hit"] == 1
+    k = hits["lod"][h]
+    nr = n_rle[hits["chunk"][h], k]
+    steps = np.ceil(np.log2(np.maximum(nr, 1)))
+    b[h] += 28.0 + 4.0 * (chunk_log2 - k - 2) + 4.0 * steps + 1.0
+    return b
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="map512", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=2025)
+    ap.add_argument("--views", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle legs (CPU baseline and visit counts)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-baseline time")
+    ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (scale for HBM byte counters)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "launches": 3}))
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path does not "
+              "shard across GPUs in this build (see DESIGN.md, sharding).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2505_02017_amd import scenes, svdag
+    svdag.lib()  # fails loudly if the HIP library is missing
+    assert torch.cuda.is_available(), "no GPU"
+
+    kind, lod_count, thr, wdesc = WORKLOADS[args.workload]
+    sw = scenes.SceneWorld(kind, args.seed)
+    CL = sw.chunk_log2
+    gx, gy, gz = sw.grid
+    nch = gx * gy * gz
+    cams = sw.views(args.views, 1)
+    W, H = cams[0].width, cams[0].height
+    use_oracle = not args.no_cpu_baseline
+
+    # ---- oracle side: which (chunk, LOD) DAGs the sampled views need
+    ow = None
+    n_rle = np.ones((nch, 4), np.int64)
+    need = [set() for _ in range(nch)]
+    if use_oracle:
+        import oracle
+        ow = oracle.World(CL, sw.grid, lod_count)
+        frames = [oracle.camera_frame(c) for c in cams]
+        view_lods = [ow.lod_pick(f.O, thr) for f in frames]
+        for vl in view_lods:
+            for ci in range(nch):
+                need[ci].add(int(vl[ci]))
+
+    # ---- generate every chunk once; build the library blob (all LODs) and
+    #      the oracle's DAGs for the LODs the sampled views use
+    t0 = time.time()
+    blobs = {}
+
+    def work(ci):
+        c = (ci % gx, (ci // gx) % gy, ci // (gx * gy))
+        g = sw.chunk(c, threads=1 if nch > 1 else args.threads)
+        b = svdag.svd_chunk_build(g, CL, lod_count)
+        odags = []
+        if ow is not None and need[ci]:
+            pyr = oracle.pyramid(g, 1 << CL, max(need[ci]) + 1)
+            for k in sorted(need[ci]):
+                odags.append((k, oracle.Dag(pyr[k], (1 << CL) >> k)))
+        return ci, b, odags
+
+    with ThreadPoolExecutor(args.threads) as ex:
+        for ci, b, odags in ex.map(work, range(nch)):
+            blobs[ci] = b
+            for k, d in odags:
+                n_rle[ci, k] = d.d.n_rle
+                ow.set_dag(ci, k, d)
+            if (ci + 1) % 32 == 0:
+                log(f"  {ci + 1}/{nch} chunks built ({time.time() - t0:.1f}s)")
+    log(f"built {nch} chunks ({lod_count} LODs) in {time.time() - t0:.1f}s")
+
+    desc = svdag.make_desc(CL, sw.grid, lod_count, thr)
+    dev_bytes = sum(svdag.svd_blob_stats_get(b, k)["device_bytes"] for b in blobs.values()
+                    for k in range(lod_count))
+    pool = torch.empty(svdag.table_bytes(sw.grid) + dev_bytes + 256 * nch, dtype=torch.uint8,
+                       device="cuda")
+    world = svdag.svd_world_create(desc, pool)
+    for ci, b in blobs.items():
+        svdag.svd_chunk_upload(world, (ci % gx, (ci // gx) % gy, ci // (gx * gy)), b)
+    torch.cuda.synchronize()
+    log(f"uploaded {dev_bytes / 2**20:.1f} MiB of chunk DAGs")
+
+    frames_gpu = [svdag.svd_camera_frame(c) for c in cams]
+    out = torch.empty((W * H, 4), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(i, ev=None):
+        f = frames_gpu[i % len(frames_gpu)]
+        if ev is not None:
+            ev[0].record(stream)
+        svdag.svd_view_stage(world, f, 0, stream)
+        if ev is not None:
+            ev[1].record(stream)
+        svdag.svd_view_trace(world, f, out, stream)
+        if ev is not None:
+            ev[2].record(stream)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step(i, evs[i])
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    stage_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    trace_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
+    view_ms = stage_ms + trace_ms
+    rays = W * H * args.steps
+    value = rays / t_total / 1e9
+
+    raw = out.cpu().numpy()
+    hits = svdag.decode_hits(raw)
+    assert not np.any(hits["chunk"] == svdag.FAULT_CHUNK), "iteration guard fired"
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "Grays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_total * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": wdesc, "chunks": nch, "chunk_edge": 1 << CL, "lods": lod_count,
+                   "width": W, "height": H, "views": len(cams), "seed": args.seed},
+        "p50_view_ms": round(float(np.percentile(view_ms, 50)), 4),
+        "p99_view_ms": round(float(np.percentile(view_ms, 99)), 4),
+        "trace_kernel_ms_mean": round(float(trace_ms.mean()), 4),
+        "stage_kernel_ms_mean": round(float(stage_ms.mean()), 4),
+        "hit_fraction": round(float(hits["hit"].mean()), 4),
+    }
+
+    if use_oracle:
+        # ---- algorithmic bytes per ray: oracle visit counts on a sparse sample of every view
+        stride = 97
+        per_ray = []
+        for v, f in enumerate(frames):
+            idx = np.arange(v % stride, W * H, stride, dtype=np.uint32)
+            h, cnt = ow.trace_frame(view_lods[v], f, idx, mode=1, threads=args.threads, counts=True)
+            per_ray.append(bytes_per_ray(cnt, h, view_lods[v], CL, n_rle))
+        mean_b = float(np.concatenate(per_ray).mean())
+        # per-view launches cycle over the views; weight each view's bytes by its launches
+        nviews = len(frames)
+        view_b = np.array([p.mean() for p in per_ray])
+        launches = np.bincount(np.arange(args.steps) % nviews, minlength=nviews)
+        bytes_per_launch = float((view_b * launches).sum() / launches.sum()) * W * H
+        achieved = bytes_per_launch / (trace_ms.mean() * 1e-3) / 1e9
+        result["roofline"] = {
+            "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "kernel": "trace_kernel", "bytes_per_ray": round(mean_b, 2),
+            "bytes_per_launch": round(bytes_per_launch), "launch_ms": round(float(trace_ms.mean()), 4),
+        }
+        # ---- CPU baseline: the oracle (as is) on a bounded sample: whole views
+        #      in benchmark order while the time budget lasts, else evenly
+        #      spaced pixels of view 0
+        pilot = np.arange(0, W * H, max(1, (W * H) // 4000), dtype=np.uint32)
+        t = time.perf_counter()
+        ow.trace_frame(view_lods[0], frames[0], pilot, mode=1, threads=args.threads)
+        per = (time.perf_counter() - t) / pilot.size
+        n_budget = int(max(1000, args.cpu_seconds / max(per, 1e-12)))
+        nviews_cpu = max(1, min(nviews, n_budget // (W * H)))
+        n0 = W * H if n_budget >= W * H else n_budget
+        sample0 = np.linspace(0, W * H - 1, n0).astype(np.uint32)
+        t = time.perf_counter()
+        refs = [ow.trace_frame(view_lods[v], frames[v], sample0 if v == 0 else None, mode=1,
+                               threads=args.threads) for v in range(nviews_cpu)]
+        dt = time.perf_counter() - t
+        n = n0 + (nviews_cpu - 1) * W * H
+        # view 0 of the sample doubles as a parity spot-check of the benchmarked path
+        step(0)
+        torch.cuda.synchronize()
+        g = svdag.decode_hits(out.cpu().numpy())
+        ref = refs[0]
+        result["cpu_sample_parity"] = bool(all(
+            np.array_equal(np.where(ref["hit"] == 1, ref[f], 0), g[f][sample0])
+            for f in ("hit", "x", "y", "z", "lod", "face", "material")))
+        what = (f"all pixels of views 0..{nviews_cpu - 1}" if n0 == W * H
+                else f"{n0} evenly spaced pixels of view 0")
+        result["cpu_baseline"] = {
+            "value": round(n / dt / 1e9, 6), "unit": "Grays/s", "cores": args.threads,
+            "kind": "oracle",
+            "sample": f"{n} rays: {what} ({W}x{H}), oracle mode 1 (empty-subtree skipping), "
+                      f"{args.threads} threads, {dt:.1f}s",
+        }
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

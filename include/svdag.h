@@ -192,9 +192,22 @@ int svd_camera_frame(const svd_camera* cam, svd_ray_frame* out);
 int svd_trace_view(svd_world* w, const svd_camera* cam, svd_hit* out_dev, uint32_t flags,
                    void* stream);
 /* Same, from an integer frame (directions must satisfy |D| < 2^31 over the
- * image and the origin the camera range above). */
+ * image and the origin the camera range above).  Equivalent to
+ * svd_view_stage followed by svd_view_trace. */
 int svd_trace_frame(svd_world* w, const svd_ray_frame* frame, svd_hit* out_dev, uint32_t flags,
                     void* stream);
+
+/* The two halves of a traced view, for callers that time or schedule them
+ * separately.
+ * svd_view_stage: the chunk stage (Section 3.5 chunk selection pass): per
+ *   chunk, the LOD by camera distance (Eq. 1) and a conservative frustum
+ *   cull of its tight box at that LOD, written to the world's view table.
+ *   Errors as svd_trace_frame.
+ * svd_view_trace: the per-pixel trace (Section 3.5 ray marching and colour
+ *   resolve) over the view table of the last svd_view_stage, which must have
+ *   been given an identical frame (else SVD_EINVAL). */
+int svd_view_stage(svd_world* w, const svd_ray_frame* frame, uint32_t flags, void* stream);
+int svd_view_trace(svd_world* w, const svd_ray_frame* frame, svd_hit* out_dev, void* stream);
 
 /* Per-chunk LOD (bits 0-1), culled (bit 2) and empty (bit 3) flags of the
  * last traced view, copied to host (synchronises `stream`). */

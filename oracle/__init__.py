@@ -23,6 +23,10 @@ HIT_DTYPE = np.dtype([
 ])
 
 
+COUNT_DTYPE = np.dtype([("chunk_visits", np.int32), ("chunk_entries", np.int32),
+                        ("node_cubes", np.int32), ("leaf_cubes", np.int32)])
+
+
 class _Frame(ctypes.Structure):
     _fields_ = [("O", ctypes.c_int64 * 3), ("A", ctypes.c_int64 * 3),
                 ("BX", ctypes.c_int64 * 3), ("BY", ctypes.c_int64 * 3),
@@ -84,7 +88,7 @@ def _lib():
         L.or_world_set_dense.argtypes = [vp, u32, u32, vp]
         L.or_lod_pick.argtypes = [vp, vp, vp, vp]
         L.or_trace.argtypes = [vp, vp, vp, vp, u32, vp, i32, i32]
-        L.or_trace_frame.argtypes = [vp, vp, ctypes.POINTER(_Frame), vp, u32, vp, i32, i32]
+        L.or_trace_frame.argtypes = [vp, vp, ctypes.POINTER(_Frame), vp, u32, vp, i32, i32, vp]
         _LIB = L
     return _LIB
 
@@ -276,7 +280,9 @@ class World:
         _lib().or_trace(self._p, _ptr(lods), _ptr(O), _ptr(D), D.shape[0], _ptr(out), mode, threads)
         return out
 
-    def trace_frame(self, lods, frame: Frame, idx=None, mode=1, threads=1) -> np.ndarray:
+    def trace_frame(self, lods, frame: Frame, idx=None, mode=1, threads=1, counts=False):
+        """Hits of the frame's pixels (all, or the indices `idx`).  With
+        counts=True also returns the per-ray visit counts (COUNT_DTYPE)."""
         lods = np.ascontiguousarray(lods, np.uint8)
         if idx is None:
             n = frame.W * frame.H
@@ -286,6 +292,7 @@ class World:
             n = idx.size
             ip = _ptr(idx)
         out = np.zeros(n, HIT_DTYPE)
+        cnt = np.zeros(n, COUNT_DTYPE) if counts else None
         _lib().or_trace_frame(self._p, _ptr(lods), ctypes.byref(frame._f), ip, n, _ptr(out),
-                              mode, threads)
-        return out
+                              mode, threads, _ptr(cnt) if counts else ctypes.c_void_p(0))
+        return (out, cnt) if counts else out

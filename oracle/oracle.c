@@ -117,19 +117,23 @@ void or_downsample(const uint8_t* src, uint32_t R, uint8_t* dst) {
   for (uint32_t z = 0; z < h; z++)
     for (uint32_t y = 0; y < h; y++)
       for (uint32_t x = 0; x < h; x++) {
-        uint32_t hist[256];
-        memset(hist, 0, sizeof(hist));
+        uint8_t m[8];
         int solid = 0;
         for (int i = 0; i < 8; i++) {
           uint32_t sx = 2 * x + (i & 1), sy = 2 * y + ((i >> 1) & 1), sz = 2 * z + ((i >> 2) & 1);
-          uint8_t m = src[(size_t)sx + (size_t)R * ((size_t)sy + (size_t)R * sz)];
-          if (m) { solid++; hist[m]++; }
+          m[i] = src[(size_t)sx + (size_t)R * ((size_t)sy + (size_t)R * sz)];
+          solid += m[i] != 0;
         }
+        /* mode of the solid children: count each value among the eight */
         uint8_t out = 0;
         if (solid >= 2) {
-          uint32_t best = 0;
-          for (int m = 1; m < 256; m++)
-            if (hist[m] > best) { best = hist[m]; out = (uint8_t)m; }
+          int best = 0;
+          for (int i = 0; i < 8; i++) {
+            if (!m[i]) continue;
+            int n = 0;
+            for (int j = 0; j < 8; j++) n += m[j] == m[i];
+            if (n > best || (n == best && m[i] < out)) { best = n; out = m[i]; }
+          }
         }
         dst[(size_t)x + (size_t)h * ((size_t)y + (size_t)h * z)] = out;
       }
@@ -642,26 +646,49 @@ typedef struct {
 /* Occupancy of world LOD-k cell c in chunk ci.  Returns 1 if solid (and the
  * material), else 0 with *skip = level (in cells) of an empty cube around it. */
 static int occupied(const or_tctx* T, uint32_t ci, uint32_t k, const int64_t c[3],
-                    const int64_t base[3], uint8_t* mat, uint32_t* skip) {
+                    const int64_t base[3], uint8_t* mat, uint32_t* skip, int32_t* elev) {
   const or_world* w = T->w;
   const size_t i = (size_t)ci * w->lod_count + k;
   const uint32_t x = (uint32_t)(c[0] - base[0]), y = (uint32_t)(c[1] - base[1]), z = (uint32_t)(c[2] - base[2]);
+  *elev = -1;
   if (T->mode & 2) {
     const uint32_t R = 1u << (w->chunk_log2 - k);
     const uint8_t m = w->dense[i] ? w->dense[i][(size_t)x + (size_t)R * ((size_t)y + (size_t)R * z)] : 0;
     *skip = 0;
     if (m) { *mat = m; return 1; }
+    *elev = 0;
     return 0;
   }
   const or_dag* d = w->dags[i];
-  if (!d) { *skip = (T->mode & 1) ? w->chunk_log2 - k : 0; return 0; }
+  if (!d) { *skip = (T->mode & 1) ? w->chunk_log2 - k : 0; *elev = (int32_t)(w->chunk_log2 - k); return 0; }
   uint32_t dfs = 0, lev = 0;
   if (or_dag_lookup(d, x, y, z, &dfs, &lev)) { *mat = or_dag_material(d, dfs); return 1; }
   *skip = (T->mode & 1) ? lev : 0;
+  *elev = (int32_t)lev;
   return 0;
 }
 
-static void trace_one(const or_tctx* T, const int64_t O[3], const int64_t D[3], or_hit* h) {
+/* Counting (test instrumentation): the non-empty cubes of the chunk's DAG
+ * that the ray enters, from the cubes around each looked-up cell above its
+ * largest empty cube.  A straight ray never re-enters a cube, so a cube is
+ * new iff it differs from the same level's cube around the previous lookup. */
+static void count_cubes(or_counts* cnt, const int64_t c[3], const int64_t base[3], int32_t elev,
+                        int top, int64_t prev[3], int* have_prev) {
+  for (int l = elev + 1; l <= top; l++) {
+    if (*have_prev && ((c[0] - base[0]) >> l) == ((prev[0] - base[0]) >> l) &&
+        ((c[1] - base[1]) >> l) == ((prev[1] - base[1]) >> l) &&
+        ((c[2] - base[2]) >> l) == ((prev[2] - base[2]) >> l))
+      continue;
+    if (l == top) cnt->chunk_entries++;
+    else if (l >= 3) cnt->node_cubes++;
+    else if (l == 2) cnt->leaf_cubes++;
+  }
+  for (int a = 0; a < 3; a++) prev[a] = c[a];
+  *have_prev = 1;
+}
+
+static void trace_one(const or_tctx* T, const int64_t O[3], const int64_t D[3], or_hit* h,
+                      or_counts* cnt) {
   const or_world* w = T->w;
   const int CL = (int)w->chunk_log2;
   const int64_t ext[3] = {(int64_t)w->grid[0] << CL, (int64_t)w->grid[1] << CL, (int64_t)w->grid[2] << CL};
@@ -685,13 +712,21 @@ static void trace_one(const or_tctx* T, const int64_t O[3], const int64_t D[3], 
       if (cc[a] < 0 || cc[a] >= (int64_t)w->grid[a]) return; /* outside the world: miss */
     const uint32_t ci = (uint32_t)(cc[0] + (int64_t)w->grid[0] * (cc[1] + (int64_t)w->grid[1] * cc[2]));
     const int k = T->lods[ci];
+    const or_dag* dk = w->dags[(size_t)ci * w->lod_count + k];
+    const int counting = cnt && !(T->mode & 2) && dk && dk->n_words;
+    int64_t prev[3] = {0, 0, 0};
+    int have_prev = 0;
+    if (cnt) cnt->chunk_visits++;
     const int64_t base[3] = {cc[0] << (CL - k), cc[1] << (CL - k), cc[2] << (CL - k)};
     int64_t c[3];
     for (int a = 0; a < 3; a++) c[a] = cell_at(O[a], D[a], cur, k);
     for (;;) {
       uint8_t mat = 0;
       uint32_t skip = 0;
-      if (occupied(T, ci, (uint32_t)k, c, base, &mat, &skip)) {
+      int32_t elev = -1;
+      const int solid = occupied(T, ci, (uint32_t)k, c, base, &mat, &skip, &elev);
+      if (counting) count_cubes(cnt, c, base, elev, CL - k, prev, &have_prev);
+      if (solid) {
         h->hit = 1;
         h->x = (int32_t)(c[0] << k); h->y = (int32_t)(c[1] << k); h->z = (int32_t)(c[2] << k);
         h->lod = k;
@@ -734,6 +769,7 @@ static void trace_one(const or_tctx* T, const int64_t O[3], const int64_t D[3], 
 
 typedef struct {
   const or_tctx* T;
+  or_counts* counts;
   const int64_t* O;
   const int32_t* D;
   const or_frame* f;
@@ -756,7 +792,8 @@ static void* trace_job(void* arg) {
       for (int a = 0; a < 3; a++) D[a] = J->D[3 * (size_t)i + a];
       O = J->O;
     }
-    trace_one(J->T, O, D, &J->out[i]);
+    if (J->counts) memset(&J->counts[i], 0, sizeof(or_counts));
+    trace_one(J->T, O, D, &J->out[i], J->counts ? &J->counts[i] : NULL);
   }
   return NULL;
 }
@@ -780,13 +817,14 @@ static void run_jobs(or_job* base, uint32_t n, int nthreads) {
 void or_trace(const or_world* w, const uint8_t* lods, const int64_t O[3], const int32_t* D,
               uint32_t n, or_hit* out, int mode, int nthreads) {
   or_tctx T = {w, lods, mode};
-  or_job J = {&T, O, D, NULL, NULL, 0, n, out};
+  or_job J = {&T, NULL, O, D, NULL, NULL, 0, n, out};
   run_jobs(&J, n, nthreads);
 }
 
 void or_trace_frame(const or_world* w, const uint8_t* lods, const or_frame* f,
-                    const uint32_t* idx, uint32_t n, or_hit* out, int mode, int nthreads) {
+                    const uint32_t* idx, uint32_t n, or_hit* out, int mode, int nthreads,
+                    or_counts* counts) {
   or_tctx T = {w, lods, mode};
-  or_job J = {&T, NULL, NULL, f, idx, 0, n, out};
+  or_job J = {&T, counts, NULL, NULL, f, idx, 0, n, out};
   run_jobs(&J, n, nthreads);
 }

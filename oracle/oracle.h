@@ -101,9 +101,19 @@ typedef struct {
  * mode bit 1: use the dense grids instead of the DAGs. */
 void or_trace(const or_world* w, const uint8_t* lods, const int64_t O[3], const int32_t* D,
               uint32_t n, or_hit* out, int mode, int nthreads);
-/* Trace the pixels idx[0..n) (idx = px + W*py) of a frame. */
+/* Per-ray visit counts of the hierarchical traversal (DAG modes only):
+ * chunks the ray passes through, non-empty chunk DAGs it enters, non-empty
+ * internal-node cubes (levels 3 .. root-1) and leaf cubes (level 2) it
+ * enters before its hit.  Used to state algorithmic memory traffic. */
+typedef struct {
+  int32_t chunk_visits, chunk_entries, node_cubes, leaf_cubes;
+} or_counts;
+
+/* Trace the pixels idx[0..n) (idx = px + W*py; all pixels if idx is NULL)
+ * of a frame; `counts` (n entries) may be NULL. */
 void or_trace_frame(const or_world* w, const uint8_t* lods, const or_frame* f,
-                    const uint32_t* idx, uint32_t n, or_hit* out, int mode, int nthreads);
+                    const uint32_t* idx, uint32_t n, or_hit* out, int mode, int nthreads,
+                    or_counts* counts);
 
 #ifdef __cplusplus
 }

@@ -130,6 +130,8 @@ struct svd_world {
   std::vector<Region> region;
   uint32_t missing = 0;  // chunks never uploaded or evicted
   size_t used = 0;
+  svd_ray_frame staged;  // frame of the last chunk stage (its view table)
+  bool has_staged = false;
 
   bool alloc(size_t bytes, size_t* off) {
     bytes = (bytes + 255) / 256 * 256;
@@ -324,10 +326,7 @@ static bool cull_planes(const svd_ray_frame* f, int64_t n[4][3]) {
   return true;
 }
 
-extern "C" int svd_trace_frame(svd_world* w, const svd_ray_frame* f, svd_hit* out_dev, uint32_t flags,
-                               void* stream) {
-  if (!w || !f || !out_dev) return svd_fail(SVD_EINVAL, "svd_trace_frame: null argument");
-  if (flags & ~SVD_NO_CULL) return svd_fail(SVD_EINVAL, "trace: unknown flags");
+static int check_frame(const svd_ray_frame* f) {
   const uint32_t W = f->width, H = f->height;
   if (W == 0 || H == 0 || (uint64_t)W * H > (1ull << 31)) return svd_fail(SVD_EINVAL, "trace: bad image size");
   for (int a = 0; a < 3; a++)
@@ -340,8 +339,21 @@ extern "C" int svd_trace_frame(svd_world* w, const svd_ray_frame* f, svd_hit* ou
         const i128 d = (i128)f->A[a] + (i128)(cpx ? W - 1 : 0) * f->BX[a] + (i128)(cpy ? H - 1 : 0) * f->BY[a];
         if (d >= lim || d <= -lim) return svd_fail(SVD_ERANGE, "trace: direction component >= 2^31");
       }
-  if (w->missing) return svd_fail(SVD_ENOTFOUND, "trace: %u chunks are not resident", w->missing);
+  return SVD_OK;
+}
 
+static bool same_frame(const svd_ray_frame& a, const svd_ray_frame& b) {
+  return memcmp(a.O, b.O, sizeof(a.O)) == 0 && memcmp(a.A, b.A, sizeof(a.A)) == 0 &&
+         memcmp(a.BX, b.BX, sizeof(a.BX)) == 0 && memcmp(a.BY, b.BY, sizeof(a.BY)) == 0 &&
+         a.width == b.width && a.height == b.height;
+}
+
+extern "C" int svd_view_stage(svd_world* w, const svd_ray_frame* f, uint32_t flags, void* stream) {
+  if (!w || !f) return svd_fail(SVD_EINVAL, "svd_view_stage: null argument");
+  if (flags & ~SVD_NO_CULL) return svd_fail(SVD_EINVAL, "stage: unknown flags");
+  int rc = check_frame(f);
+  if (rc) return rc;
+  if (w->missing) return svd_fail(SVD_ENOTFOUND, "stage: %u chunks are not resident", w->missing);
   StageParams sp;
   memset(&sp, 0, sizeof(sp));
   memcpy(sp.O, f->O, sizeof(sp.O));
@@ -353,9 +365,19 @@ extern "C" int svd_trace_frame(svd_world* w, const svd_ray_frame* f, svd_hit* ou
   sp.nchunks = w->nchunks;
   sp.desc = w->d_desc;
   sp.view = w->d_view;
-  int rc = launch_chunk_stage(sp, stream);
+  rc = launch_chunk_stage(sp, stream);
   if (rc) return rc;
+  w->staged = *f;
+  w->has_staged = true;
+  return SVD_OK;
+}
 
+extern "C" int svd_view_trace(svd_world* w, const svd_ray_frame* f, svd_hit* out_dev, void* stream) {
+  if (!w || !f || !out_dev) return svd_fail(SVD_EINVAL, "svd_view_trace: null argument");
+  if (!w->has_staged || !same_frame(w->staged, *f))
+    return svd_fail(SVD_EINVAL, "trace: the frame was not staged by the last svd_view_stage");
+  if (w->missing) return svd_fail(SVD_ENOTFOUND, "trace: %u chunks are not resident", w->missing);
+  const uint32_t W = f->width, H = f->height;
   TraceParams tp;
   memset(&tp, 0, sizeof(tp));
   memcpy(tp.O, f->O, sizeof(tp.O));
@@ -372,6 +394,14 @@ extern "C" int svd_trace_frame(svd_world* w, const svd_ray_frame* f, svd_hit* ou
   tp.desc = w->d_desc;
   tp.out = out_dev;
   return launch_trace(tp, stream);
+}
+
+extern "C" int svd_trace_frame(svd_world* w, const svd_ray_frame* f, svd_hit* out_dev, uint32_t flags,
+                               void* stream) {
+  if (!w || !f || !out_dev) return svd_fail(SVD_EINVAL, "svd_trace_frame: null argument");
+  int rc = svd_view_stage(w, f, flags, stream);
+  if (rc) return rc;
+  return svd_view_trace(w, f, out_dev, stream);
 }
 
 extern "C" int svd_trace_view(svd_world* w, const svd_camera* cam, svd_hit* out_dev, uint32_t flags,

@@ -121,6 +121,73 @@ static void fbm3_row(uint64_t seed, int64_t x0, int64_t n, int64_t y, int64_t z,
   for (int64_t t = 0; t < n; t++) out[t] /= w;
 }
 
+/*
+ * Lattice values of a 3D fBm over one chunk, precomputed per octave, so that
+ * rows of the chunk interpolate without rehashing.  Same values and the same
+ * interpolation order as fbm3_row, hence identical results.
+ */
+typedef struct {
+  int octaves;
+  int64_t lam0;
+  uint64_t seed;
+  int64_t i0[8], j0[8], k0[8], n[8];
+  double* v[8];
+} sg_lattice;
+
+static void lattice_init(sg_lattice* L, uint64_t seed, int octaves, int64_t lam0, int64_t X0, int64_t Y0,
+                         int64_t Z0, int64_t S) {
+  L->octaves = octaves;
+  L->lam0 = lam0;
+  L->seed = seed;
+  for (int o = 0; o < octaves; o++) {
+    const uint64_t so = seed + 0x1000ull * (uint64_t)o;
+    const int sh = ilog2_i64(lam0 >> o);
+    const int64_t n = ((S - 1) >> sh) + 3;
+    L->i0[o] = X0 >> sh; L->j0[o] = Y0 >> sh; L->k0[o] = Z0 >> sh; L->n[o] = n;
+    L->v[o] = (double*)malloc((size_t)(n * n * n) * sizeof(double));
+    for (int64_t c = 0; c < n; c++)
+      for (int64_t b = 0; b < n; b++)
+        for (int64_t a = 0; a < n; a++)
+          L->v[o][a + n * (b + n * c)] = lattice(so, L->i0[o] + a, L->j0[o] + b, L->k0[o] + c);
+  }
+}
+
+static void lattice_free(sg_lattice* L) {
+  for (int o = 0; o < L->octaves; o++) free(L->v[o]);
+}
+
+static void fbm3_row_tab(const sg_lattice* L, int64_t x0, int64_t nx, int64_t y, int64_t z, double* out,
+                         double* scratch) {
+  double w = 0.0, amp = 1.0;
+  double fx_tab[1024];
+  for (int64_t t = 0; t < nx; t++) out[t] = 0.0;
+  for (int o = 0; o < L->octaves; o++) {
+    const int64_t lam = L->lam0 >> o;
+    const int sh = ilog2_i64(lam);
+    const int64_t j = y >> sh, k = z >> sh, n = L->n[o];
+    const double fy = fade((double)(y - (j << sh)) / (double)lam);
+    const double fz = fade((double)(z - (k << sh)) / (double)lam);
+    const int64_t i0 = x0 >> sh, i1 = ((x0 + nx - 1) >> sh) + 1;
+    const double* V = L->v[o];
+    const int64_t jb = j - L->j0[o], kb = k - L->k0[o];
+    for (int64_t i = i0; i <= i1; i++) {
+      const int64_t ia = i - L->i0[o];
+      double a = lerp(V[ia + n * (jb + n * kb)], V[ia + n * (jb + 1 + n * kb)], fy);
+      double b = lerp(V[ia + n * (jb + n * (kb + 1))], V[ia + n * (jb + 1 + n * (kb + 1))], fy);
+      scratch[i - i0] = lerp(a, b, fz);
+    }
+    for (int64_t r = 0; r < lam; r++) fx_tab[r] = fade((double)r / (double)lam);
+    for (int64_t t = 0; t < nx; t++) {
+      const int64_t x = x0 + t;
+      const int64_t i = (x >> sh) - i0;
+      out[t] += amp * lerp(scratch[i], scratch[i + 1], fx_tab[x & (lam - 1)]);
+    }
+    w += amp;
+    amp *= 0.5;
+  }
+  for (int64_t t = 0; t < nx; t++) out[t] /= w;
+}
+
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
@@ -277,6 +344,7 @@ typedef struct {
   uint32_t cx, cy, cz;
   int64_t za, zb;
   const int64_t* hh;
+  const sg_lattice* cave;
   uint8_t* out;
 } sg_job;
 
@@ -287,7 +355,6 @@ static void* gen_terrain_slab(void* arg) {
   const int64_t X0 = (int64_t)J->cx * S, Y0 = (int64_t)J->cy * S, Z0 = (int64_t)J->cz * S;
   double* row = (double*)malloc((size_t)S * sizeof(double));
   double* scr = (double*)malloc((size_t)(S + 8) * sizeof(double));
-  const uint64_t cave_seed = w->seed ^ 0xCA7ECA7Eull;
   for (int64_t z = J->za; z < J->zb; z++) {
     const int64_t Z = Z0 + z;
     const uint8_t band = (uint8_t)(1 + (8 * Z) / w->zmax);
@@ -300,7 +367,7 @@ static void* gen_terrain_slab(void* arg) {
         need_cave |= (Z < hr[x] - 4);
       }
       if (!any) { memset(o, 0, (size_t)S); continue; }
-      if (need_cave) fbm3_row(cave_seed, X0, S, Y0 + y, Z, 2, w->cave_lam, row, scr);
+      if (need_cave) fbm3_row_tab(J->cave, X0, S, Y0 + y, Z, row, scr);
       for (int64_t x = 0; x < S; x++) {
         uint8_t m = 0;
         if (Z <= hr[x]) {
@@ -325,16 +392,19 @@ static void gen_terrain(const sg_world* w, uint32_t cx, uint32_t cy, uint32_t cz
   if (nthreads < 1) nthreads = 1;
   if (nthreads > 64) nthreads = 64;
   if (nthreads > S) nthreads = (int)S;
+  sg_lattice cave;
+  lattice_init(&cave, w->seed ^ 0xCA7ECA7Eull, 2, w->cave_lam, X0, Y0, Z0, S);
   sg_job jobs[64];
   pthread_t th[64];
   for (int t = 0; t < nthreads; t++) {
     jobs[t].w = w; jobs[t].cx = cx; jobs[t].cy = cy; jobs[t].cz = cz;
     jobs[t].za = S * t / nthreads; jobs[t].zb = S * (t + 1) / nthreads;
-    jobs[t].hh = hh; jobs[t].out = out;
+    jobs[t].hh = hh; jobs[t].cave = &cave; jobs[t].out = out;
   }
   for (int t = 1; t < nthreads; t++) pthread_create(&th[t], NULL, gen_terrain_slab, &jobs[t]);
   gen_terrain_slab(&jobs[0]);
   for (int t = 1; t < nthreads; t++) pthread_join(th[t], NULL);
+  lattice_free(&cave);
   /* boxes overwrite terrain; later boxes overwrite earlier ones */
   for (int b = 0; b < w->nbox; b++) {
     const sg_box* bx = &w->boxes[b];

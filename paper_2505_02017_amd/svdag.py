@@ -33,7 +33,7 @@ EXPORTS = [
     "svd_blob_free", "svd_free", "svd_blob_stats_get", "svd_blob_canonical",
     "svd_world_create", "svd_world_destroy", "svd_world_pool_used", "svd_chunk_upload",
     "svd_chunk_evict", "svd_camera_frame", "svd_trace_view", "svd_trace_frame",
-    "svd_view_table",
+    "svd_view_stage", "svd_view_trace", "svd_view_table",
 ]
 
 
@@ -100,6 +100,8 @@ def lib() -> ctypes.CDLL:
         L.svd_trace_view.argtypes = [vp, ctypes.POINTER(svd_camera), vp, u32, vp]
         L.svd_trace_frame.argtypes = [vp, ctypes.POINTER(svd_ray_frame), vp, u32, vp]
         L.svd_view_table.argtypes = [vp, ctypes.POINTER(u32), u32, vp]
+        L.svd_view_stage.argtypes = [vp, ctypes.POINTER(svd_ray_frame), u32, vp]
+        L.svd_view_trace.argtypes = [vp, ctypes.POINTER(svd_ray_frame), vp, vp]
         for n in EXPORTS:
             if n not in ("svd_last_error", "svd_blob_free", "svd_free", "svd_world_destroy"):
                 getattr(L, n).restype = i32
@@ -308,6 +310,15 @@ def svd_trace_view(w: World, cam, out, flags: int = 0, stream=None):
 def svd_trace_frame(w: World, frame: svd_ray_frame, out, flags: int = 0, stream=None):
     _check(lib().svd_trace_frame(w.ptr, ctypes.byref(frame), _out_ptr(out, frame.width * frame.height),
                                  flags, _stream_ptr(stream)))
+
+
+def svd_view_stage(w: World, frame: svd_ray_frame, flags: int = 0, stream=None):
+    _check(lib().svd_view_stage(w.ptr, ctypes.byref(frame), flags, _stream_ptr(stream)))
+
+
+def svd_view_trace(w: World, frame: svd_ray_frame, out, stream=None):
+    _check(lib().svd_view_trace(w.ptr, ctypes.byref(frame), _out_ptr(out, frame.width * frame.height),
+                                _stream_ptr(stream)))
 
 
 def svd_view_table(w: World, stream=None) -> np.ndarray:
