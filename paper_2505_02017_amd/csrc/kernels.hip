@@ -4,9 +4,15 @@
 // p(t) = (O + t D) / 2^16 voxels with integer O, D.  A time is a rational
 // Nt/Dt plus a phase (0 = at t, 1 = just after t); a boundary crossing on an
 // axis with D > 0 takes effect at t, one with D < 0 just after t, so events
-// are ordered by (t, class) and equal keys are stepped together.  Every
-// comparison is a cross-multiplication of 32-bit values (one v_mad_u64_u32),
-// with no division in the loop.
+// are ordered by (t, class) and equal keys are stepped together.
+//
+// Each ray is mirrored on the axes where D < 0 (as ESVO does), so that every
+// direction component is >= 0 and every cell coordinate only grows; a
+// mirrored axis keeps class 1 (its cells are closed at their upper plane).
+// Then "the ray is past plane X of axis a" is the single key comparison
+// ((X - O_a) / |D_a|, class_a) <= (Nt / Dt, phase), one 32x32->64-bit
+// multiply against R_a = Nt |D_a|, which is recomputed once per step.  No
+// division anywhere in the kernel.
 //
 // The walk is one hierarchy: chunk grid (level chunk_log2, in voxels), the
 // chunk's DAG levels down to 8^3 nodes (level k+3 for LOD k), the 4^3 leaf
@@ -14,7 +20,8 @@
 // the child containing the current instant is found with three mid-plane
 // tests; an empty child is left by one exact step at its level, followed by
 // a pop to the lowest common ancestor of the old and new cells (highest
-// differing coordinate bit).  The node words of the current path live in LDS.
+// changed coordinate bit).  The node words of the current path live in LDS.
+// Hits are resolved after the loop (DFS index, material run, t, face).
 #include <hip/hip_runtime.h>
 
 #include "svdag_internal.h"
@@ -46,13 +53,11 @@ int launch_set_desc(DevDag* dst, const DevDag* src, uint32_t n, void* stream) {
 // 128-bit integers.  Cull: the chunk's tight box at that LOD lies strictly on
 // the outer side of a side plane of the view cone (exact 128-bit), so no
 // pixel ray can reach a solid cell of it.
-__global__ void chunk_stage_kernel(StageParams p) {
-  const uint32_t ci = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ci >= p.nchunks) return;
+__host__ __device__ inline uint32_t stage_chunk(const StageParams& p, uint32_t ci) {
   const uint32_t cc[3] = {ci % p.grid[0], (ci / p.grid[0]) % p.grid[1], ci / (p.grid[0] * p.grid[1])};
   const int64_t S = (int64_t)1 << p.chunk_log2;
   unsigned __int128 d2 = 0;
-  for (int a = 0; a < 3; a++) {
+  _Pragma("unroll") for (int a = 0; a < 3; a++) {
     const __int128 diff = (__int128)p.O[a] - (__int128)(((int64_t)cc[a] * S + S / 2) << 16);
     d2 += (unsigned __int128)(diff * diff);
   }
@@ -67,7 +72,7 @@ __global__ void chunk_stage_kernel(StageParams p) {
     v |= kViewEmpty;
   } else if (p.cull) {
     __int128 lo[3], hi[3];
-    for (int a = 0; a < 3; a++) {
+    _Pragma("unroll") for (int a = 0; a < 3; a++) {
       const int64_t base = (int64_t)cc[a] * S;
       lo[a] = ((__int128)(base + ((int64_t)d.lo[a] << k)) << 16) - p.O[a];
       hi[a] = ((__int128)(base + ((int64_t)(d.hi[a] + 1) << k)) << 16) - p.O[a];
@@ -75,12 +80,18 @@ __global__ void chunk_stage_kernel(StageParams p) {
     bool culled = false;
     for (int i = 0; i < 4; i++) {
       __int128 s = 0;
-      for (int a = 0; a < 3; a++) s += (__int128)p.n[i][a] * (p.n[i][a] >= 0 ? hi[a] : lo[a]);
+      _Pragma("unroll") for (int a = 0; a < 3; a++) s += (__int128)p.n[i][a] * (p.n[i][a] >= 0 ? hi[a] : lo[a]);
       if (s < 0) culled = true;
     }
     if (culled) v |= kViewCulled;
   }
-  p.view[ci] = v;
+  return v;
+}
+
+__global__ void chunk_stage_kernel(StageParams p) {
+  const uint32_t ci = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ci >= p.nchunks) return;
+  p.view[ci] = stage_chunk(p, ci);
 }
 
 int launch_chunk_stage(const StageParams& p, void* stream) {
@@ -98,26 +109,231 @@ constexpr int kStackLevels = 8;  // node levels 3..10
 constexpr uint32_t kMaxIter = 1u << 22;
 constexpr uint32_t kFaultChunk = 0xFFFFFFFEu;
 
-// Is p_a >= X (fixed point) at the current instant?
-__device__ __forceinline__ bool plane_ge(int64_t X, int64_t O, int dsg, uint32_t ad, uint32_t Nt,
-                                         uint32_t Dt, uint32_t ph) {
-  const int64_t U = X - O;
-  if (dsg > 0) return U <= 0 || (uint64_t)(uint32_t)U * Dt <= (uint64_t)Nt * ad;
-  if (dsg < 0) {
-    if (U > 0) return false;
-    const uint64_t l = (uint64_t)Nt * ad, r = (uint64_t)(uint32_t)(-U) * Dt;
-    return ph ? (l < r) : (l <= r);
-  }
-  return U <= 0;
-}
+enum : uint32_t { kRunning = 0, kHit = 1, kMiss = 2, kFault = 3 };
 
 // 8-bit mask of the non-empty bytes of a leaf bitmap (= non-empty 2^3 sub-blocks).
-__device__ __forceinline__ uint32_t leaf_summary(uint64_t b) {
+__host__ __device__ __forceinline__ uint32_t float_bits(float f) {
+  union { float f; uint32_t u; } v;
+  v.f = f;
+  return v.u;
+}
+
+__host__ __device__ __forceinline__ uint32_t leaf_summary(uint64_t b) {
   b |= b >> 4;
   b |= b >> 2;
   b |= b >> 1;
   b &= 0x0101010101010101ull;
   return (uint32_t)((b * 0x0102040810204080ull) >> 56);
+}
+
+// Ray in mirrored coordinates and its current instant.
+struct Ray {
+  int64_t Om[3];   // mirrored origin, voxels * 2^16
+  uint32_t ad[3];  // |D_a|
+  uint32_t mm;     // mirror mask (bit a: D_a < 0) = class bits
+  uint32_t Nt, Dt, ph;
+  uint64_t R[3];   // Nt * ad[a]
+
+  // Has the current instant passed plane X16 (mirrored, voxels*2^16) of axis a?
+  __host__ __device__ __forceinline__ bool past(int a, int64_t X16) const {
+    const int64_t N = X16 - Om[a];
+    const uint64_t L = (uint64_t)(uint32_t)N * Dt;
+    return N < 0 || L < R[a] || (L == R[a] && ((mm >> a) & 1u) <= ph);
+  }
+  __host__ __device__ __forceinline__ void set_time(uint32_t n, uint32_t d, uint32_t cls) {
+    Nt = n;
+    Dt = d;
+    ph = cls;
+    _Pragma("unroll") for (int a = 0; a < 3; a++) R[a] = (uint64_t)Nt * ad[a];
+  }
+};
+
+// The whole per-pixel path: ray setup, world entry, chunk walk, DAG
+// traversal, hit resolve.  `stk` is this ray's node-word stack (levels 3..10,
+// element stride `ss`).
+__host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, uint32_t py,
+                                             uint32_t* stk, uint32_t ss) {
+  const int CL = (int)p.chunk_log2;
+  int32_t D[3];
+  Ray r;
+  r.mm = 0;
+  _Pragma("unroll") for (int a = 0; a < 3; a++) {
+    D[a] = (int32_t)(p.A[a] + (int64_t)px * p.BX[a] + (int64_t)py * p.BY[a]);
+    r.ad[a] = (uint32_t)(D[a] < 0 ? -(int64_t)D[a] : (int64_t)D[a]);
+    const int64_t ext16 = (int64_t)p.grid[a] << (CL + 16);
+    if (D[a] < 0) r.mm |= 1u << a;
+    r.Om[a] = D[a] < 0 ? ext16 - p.O[a] : p.O[a];
+  }
+
+  // World entry: the latest lower bound of the per-axis slabs (mirrored
+  // world = [0, ext) per axis, entered through plane 0).
+  uint32_t n0 = 0, d0 = 1, c0 = 0;
+  _Pragma("unroll") for (int a = 0; a < 3; a++) {
+    // a class-1 axis starting exactly on plane 0 still enters just after t = 0
+    if (r.Om[a] > 0 || r.ad[a] == 0) continue;
+    const uint32_t n = (uint32_t)(-r.Om[a]), cls = (r.mm >> a) & 1u;
+    const uint64_t l = (uint64_t)n * d0, q = (uint64_t)n0 * r.ad[a];
+    if (l > q || (l == q && cls > c0)) { n0 = n; d0 = r.ad[a]; c0 = cls; }
+  }
+  r.set_time(n0, d0, c0);
+
+  uint32_t status = kRunning;
+  int32_t c[3];
+  _Pragma("unroll") for (int a = 0; a < 3; a++) {
+    const int64_t ext16 = (int64_t)p.grid[a] << (CL + 16);
+    if (!r.past(a, 0) || r.past(a, ext16)) status = kMiss;
+    // chunk coordinate at the entry instant: binary search over chunk planes
+    uint32_t lo = 0, hi = p.grid[a];
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (r.past(a, (int64_t)mid << (CL + 16))) lo = mid; else hi = mid;
+    }
+    c[a] = (int32_t)lo;
+  }
+
+  int lev = CL, k = 0;
+  bool at_chunk = true;
+  uint32_t mask = 0, ptr = 0, ci = 0, iter = 0;
+  uint64_t bitmap = 0;
+  const uint32_t* nodes = nullptr;
+  const uint64_t* leaves = nullptr;
+  while (status == kRunning) {
+    if (++iter > kMaxIter) { status = kFault; break; }
+    bool step = false;
+    if (at_chunk) {
+      if (c[0] >= (int32_t)p.grid[0] || c[1] >= (int32_t)p.grid[1] || c[2] >= (int32_t)p.grid[2]) {
+        status = kMiss;  // left the world
+        break;
+      }
+      uint32_t co[3];
+      _Pragma("unroll") for (int a = 0; a < 3; a++) co[a] = ((r.mm >> a) & 1u) ? p.grid[a] - 1 - (uint32_t)c[a] : (uint32_t)c[a];
+      ci = co[0] + p.grid[0] * (co[1] + p.grid[1] * co[2]);
+      const uint32_t v = p.view[ci];
+      if (v & (kViewCulled | kViewEmpty)) {
+        step = true;
+      } else {
+        k = (int)(v & kViewLodMask);
+        const DevDag* dag = &p.desc[(size_t)ci * 4 + k];
+        nodes = (const uint32_t*)dag->nodes;
+        leaves = (const uint64_t*)dag->leaves;
+        const uint32_t root = dag->root;
+        stk[(CL - 3) * ss] = root;
+        mask = root >> kPtrBits;
+        ptr = 0;
+        at_chunk = false;
+      }
+    }
+    if (!step) {
+      // descend: the child of cell c (level lev) holding the current instant
+      uint32_t bits = 0;
+      _Pragma("unroll") for (int a = 0; a < 3; a++) {
+        const uint32_t b = r.past(a, (int64_t)(2 * c[a] + 1) << (lev - 1 + 16)) ? 1u : 0u;
+        c[a] = 2 * c[a] + (int32_t)b;
+        bits |= b << a;
+      }
+      lev--;
+      const uint32_t oct = bits ^ r.mm;  // octant in the unmirrored node
+      if ((mask >> oct) & 1u) {
+        if (lev == k) { status = kHit; break; }
+        if (lev >= k + 3) {
+          const uint32_t w = nodes[ptr + __builtin_popcount(mask & ((1u << oct) - 1u))];
+          stk[(lev - 3) * ss] = w;
+          mask = w >> kPtrBits;
+          ptr = w & kPtrMask;
+        } else if (lev == k + 2) {
+          const uint32_t w = nodes[ptr + __builtin_popcount(mask & ((1u << oct) - 1u))];
+          bitmap = leaves[w & kPtrMask];
+          mask = leaf_summary(bitmap);
+        } else {
+          mask = (uint32_t)(bitmap >> (8 * oct)) & 0xFFu;
+        }
+        continue;
+      }
+    }
+    // ---- step out of the empty cell c at level lev: earliest exit plane
+    uint32_t bn = 0, bd = 0, bc = 0, sm = 0;
+    _Pragma("unroll") for (int a = 0; a < 3; a++) {
+      const uint32_t n = (uint32_t)((((int64_t)c[a] + 1) << (lev + 16)) - r.Om[a]);
+      const uint32_t cls = (r.mm >> a) & 1u;
+      if (a == 0) { bn = n; bd = r.ad[0]; bc = cls; sm = 1u; continue; }
+      const uint64_t l = (uint64_t)n * bd, q = (uint64_t)bn * r.ad[a];
+      if (l < q || (l == q && cls < bc)) { bn = n; bd = r.ad[a]; bc = cls; sm = 1u << a; }
+      else if (l == q && cls == bc) sm |= 1u << a;
+    }
+    if (bd == 0) { status = kMiss; break; }  // D == 0: the ray never leaves this cell
+    r.set_time(bn, bd, bc);
+    uint32_t diff = 0;
+    _Pragma("unroll") for (int a = 0; a < 3; a++) {
+      if (!((sm >> a) & 1u)) continue;
+      diff |= (uint32_t)(c[a] ^ (c[a] + 1));
+      c[a] += 1;
+    }
+    const int pl = lev + (32 - __builtin_clz(diff));  // lowest common ancestor level
+    if (pl > CL) {
+      _Pragma("unroll") for (int a = 0; a < 3; a++) c[a] >>= (CL - lev);
+      lev = CL;
+      at_chunk = true;
+      continue;
+    }
+    _Pragma("unroll") for (int a = 0; a < 3; a++) c[a] >>= (pl - lev);
+    lev = pl;
+    if (lev >= k + 3) {
+      const uint32_t w = stk[(lev - 3) * ss];
+      mask = w >> kPtrBits;
+      ptr = w & kPtrMask;
+    } else if (lev == k + 2) {
+      mask = leaf_summary(bitmap);
+    } else {
+      const uint32_t o1 = (((uint32_t)c[0] & 1u) | (((uint32_t)c[1] & 1u) << 1) | (((uint32_t)c[2] & 1u) << 2)) ^ r.mm;
+      mask = (uint32_t)(bitmap >> (8 * o1)) & 0xFFu;
+    }
+  }
+
+  uint4 rec = make_uint4(0u, 0u, 0x7F800000u /* +inf */, 0xFFFFFFFFu);
+  if (status == kFault) rec.w = kFaultChunk;
+  if (status == kHit) {
+    // unmirrored LOD-k cell
+    int32_t h[3];
+    _Pragma("unroll") for (int a = 0; a < 3; a++)
+      h[a] = ((r.mm >> a) & 1u) ? (int32_t)((p.grid[a] << (CL - k)) - 1) - c[a] : c[a];
+    const DevDag* dag = &p.desc[(size_t)ci * 4 + k];
+    // DFS index (Section 3.3): counts of earlier siblings along the path
+    const uint32_t* pre = (const uint32_t*)dag->pre;
+    uint32_t dfs = 0;
+    for (int L = CL; L >= k + 3; L--) {
+      const uint32_t w = stk[(L - 3) * ss];
+      const int s = L - 1 - k;
+      const uint32_t o = ((h[0] >> s) & 1) | (((h[1] >> s) & 1) << 1) | (((h[2] >> s) & 1) << 2);
+      dfs += pre[(w & kPtrMask) + __builtin_popcount((w >> kPtrBits) & ((1u << o) - 1u))];
+    }
+    const uint32_t o1 = ((h[0] >> 1) & 1) | (((h[1] >> 1) & 1) << 1) | (((h[2] >> 1) & 1) << 2);
+    const uint32_t o0 = (h[0] & 1) | ((h[1] & 1) << 1) | ((h[2] & 1) << 2);
+    dfs += (uint32_t)__builtin_popcountll(bitmap & ((1ull << (8 * o1 + o0)) - 1ull));
+    // material: the last run starting at or before the DFS index
+    const uint32_t* rs = (const uint32_t*)dag->rle_start;
+    uint32_t lo = 0, hi = dag->rle_n;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (rs[mid] <= dfs) lo = mid; else hi = mid;
+    }
+    const uint32_t mat = ((const uint8_t*)dag->rle_mat)[lo];
+    // entry face: lowest axis whose entry plane is crossed at the hit instant
+    uint32_t face = 0;
+    _Pragma("unroll") for (int a = 0; a < 3; a++) {
+      if (face || !D[a]) continue;
+      const uint32_t cls = (r.mm >> a) & 1u;
+      const int64_t X16 = (int64_t)(cls ? h[a] + 1 : h[a]) << (k + 16);
+      const int64_t ne = cls ? p.O[a] - X16 : X16 - p.O[a];
+      if (ne >= 0 && cls == r.ph && (uint64_t)ne * r.Dt == (uint64_t)r.Nt * r.ad[a]) face = 1 + 2 * a + cls;
+    }
+    const double len = sqrt((double)D[0] * D[0] + (double)D[1] * D[1] + (double)D[2] * D[2]);
+    const float t = (float)(((double)r.Nt / (double)r.Dt) * len * (1.0 / 65536.0));
+    rec.x = ((uint32_t)h[0] << k) | (((uint32_t)h[1] << k) << 16);
+    rec.y = ((uint32_t)h[2] << k) | ((uint32_t)k << 16) | (face << 20) | (1u << 23) | (mat << 24);
+    rec.z = float_bits(t);
+    rec.w = ci;
+  }
+  return rec;
 }
 
 __global__ __launch_bounds__(kBlock) void trace_kernel(TraceParams p) {
@@ -133,186 +349,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceParams p) {
   const uint32_t px = (blk % p.tiles_x) * 16 + (wv & 1) * 8 + (lane & 7);
   const uint32_t py = (blk / p.tiles_x) * 16 + (wv >> 1) * 8 + (lane >> 3);
   if (px >= p.W || py >= p.H) return;
-
-  const int CL = (int)p.chunk_log2;
-  int dsg[3];
-  uint32_t ad[3];
-  int32_t D[3];
-  for (int a = 0; a < 3; a++) {
-    D[a] = (int32_t)(p.A[a] + (int64_t)px * p.BX[a] + (int64_t)py * p.BY[a]);
-    dsg[a] = (D[a] > 0) - (D[a] < 0);
-    ad[a] = (uint32_t)(D[a] < 0 ? -(int64_t)D[a] : (int64_t)D[a]);
-  }
-
-  // World entry: the latest lower bound of the per-axis slab intervals.
-  uint32_t Nt = 0, Dt = 1, ph = 0;
-  for (int a = 0; a < 3; a++) {
-    uint32_t n = 0, cls = 0;
-    bool cand = false;
-    if (dsg[a] > 0 && p.O[a] < 0) { n = (uint32_t)(-p.O[a]); cls = 0; cand = true; }
-    if (dsg[a] < 0) {
-      const int64_t v = p.O[a] - ((int64_t)p.grid[a] << (CL + 16));
-      if (v >= 0) { n = (uint32_t)v; cls = 1; cand = true; }
-    }
-    if (!cand) continue;
-    const uint64_t l = (uint64_t)n * Dt, r = (uint64_t)Nt * ad[a];
-    if (l > r || (l == r && cls > ph)) { Nt = n; Dt = ad[a]; ph = cls; }
-  }
-
-  uint4 rec = make_uint4(0u, 0u, __float_as_uint(__builtin_inff()), 0xFFFFFFFFu);
-  bool inside = true;
-  for (int a = 0; a < 3; a++) {
-    const int64_t ext = (int64_t)p.grid[a] << (CL + 16);
-    inside = inside && plane_ge(0, p.O[a], dsg[a], ad[a], Nt, Dt, ph) &&
-             !plane_ge(ext, p.O[a], dsg[a], ad[a], Nt, Dt, ph);
-  }
-  if (inside) {
-    // cell coordinates at the entry instant: one exact division per axis
-    int32_t c[3];
-    for (int a = 0; a < 3; a++) {
-      const uint64_t v = (uint64_t)(p.O[a] * (int64_t)Dt + (int64_t)Nt * D[a]);  // p * 2^16 * Dt >= 0
-      const uint64_t den = (uint64_t)Dt << 16;
-      uint64_t q = v / den;
-      if (dsg[a] < 0 && ph && q * den == v) q -= 1;
-      c[a] = (int32_t)(q >> CL);
-    }
-    int lev = CL, k = 0;
-    bool at_chunk = true;
-    uint32_t mask = 0, ptr = 0, ci = 0;
-    uint64_t bitmap = 0;
-    const uint32_t* nodes = nullptr;
-    const uint64_t* leaves = nullptr;
-    const DevDag* dag = nullptr;
-    uint32_t iter = 0;
-    for (;;) {
-      if (++iter > kMaxIter) { rec.w = kFaultChunk; break; }
-      bool step = false;
-      if (at_chunk) {
-        if (c[0] < 0 || c[1] < 0 || c[2] < 0 || c[0] >= (int32_t)p.grid[0] || c[1] >= (int32_t)p.grid[1] ||
-            c[2] >= (int32_t)p.grid[2])
-          break;  // left the world: miss
-        ci = (uint32_t)c[0] + p.grid[0] * ((uint32_t)c[1] + p.grid[1] * (uint32_t)c[2]);
-        const uint32_t v = p.view[ci];
-        if (v & (kViewCulled | kViewEmpty)) {
-          step = true;
-        } else {
-          k = (int)(v & kViewLodMask);
-          dag = &p.desc[(size_t)ci * 4 + k];
-          nodes = (const uint32_t*)dag->nodes;
-          leaves = (const uint64_t*)dag->leaves;
-          const uint32_t root = dag->root;
-          stk[CL - 3][tid] = root;
-          mask = root >> kPtrBits;
-          ptr = 0;
-          at_chunk = false;
-        }
-      }
-      if (!step) {
-        // descend: child octant of the current instant inside cell c (level lev)
-        uint32_t oct = 0;
-        for (int a = 0; a < 3; a++) {
-          const int64_t X = (int64_t)(2 * c[a] + 1) << (lev - 1 + 16);
-          const uint32_t bit = plane_ge(X, p.O[a], dsg[a], ad[a], Nt, Dt, ph) ? 1u : 0u;
-          c[a] = 2 * c[a] + (int32_t)bit;
-          oct |= bit << a;
-        }
-        lev--;
-        if ((mask >> oct) & 1u) {
-          if (lev == k) {
-            // ---- hit: DFS index (Section 3.3), material, t, face
-            const uint32_t* pre = (const uint32_t*)dag->pre;
-            uint32_t dfs = 0;
-            for (int L = CL; L >= k + 3; L--) {
-              const uint32_t w = stk[L - 3][tid];
-              const int s = L - 1 - k;
-              const uint32_t o = ((c[0] >> s) & 1) | (((c[1] >> s) & 1) << 1) | (((c[2] >> s) & 1) << 2);
-              dfs += pre[(w & kPtrMask) + __builtin_popcount((w >> kPtrBits) & ((1u << o) - 1u))];
-            }
-            const uint32_t o1 = ((c[0] >> 1) & 1) | (((c[1] >> 1) & 1) << 1) | (((c[2] >> 1) & 1) << 2);
-            const uint32_t o0 = (c[0] & 1) | ((c[1] & 1) << 1) | ((c[2] & 1) << 2);
-            const uint32_t b = 8 * o1 + o0;
-            dfs += (uint32_t)__builtin_popcountll(bitmap & ((1ull << b) - 1ull));
-            const uint32_t* rs = (const uint32_t*)dag->rle_start;
-            uint32_t lo = 0, hi = dag->rle_n;
-            while (hi - lo > 1) {
-              const uint32_t mid = (lo + hi) >> 1;
-              if (rs[mid] <= dfs) lo = mid; else hi = mid;
-            }
-            const uint32_t mat = ((const uint8_t*)dag->rle_mat)[lo];
-            uint32_t face = 0;
-            for (int a = 0; a < 3 && !face; a++) {
-              if (!dsg[a]) continue;
-              const int64_t X = (int64_t)(dsg[a] > 0 ? c[a] : c[a] + 1) << (k + 16);
-              const int64_t ne = dsg[a] > 0 ? X - p.O[a] : p.O[a] - X;
-              const uint32_t cls = dsg[a] < 0;
-              if (ne >= 0 && cls == ph && (uint64_t)ne * Dt == (uint64_t)Nt * ad[a]) face = 1 + 2 * a + cls;
-            }
-            const double len = sqrt((double)D[0] * D[0] + (double)D[1] * D[1] + (double)D[2] * D[2]);
-            const float t = (float)(((double)Nt / (double)Dt) * len * (1.0 / 65536.0));
-            rec.x = ((uint32_t)c[0] << k) | (((uint32_t)c[1] << k) << 16);
-            rec.y = ((uint32_t)c[2] << k) | ((uint32_t)k << 16) | (face << 20) | (1u << 23) | (mat << 24);
-            rec.z = __float_as_uint(t);
-            rec.w = ci;
-            break;
-          }
-          if (lev >= k + 3) {
-            const uint32_t w = nodes[ptr + __builtin_popcount(mask & ((1u << oct) - 1u))];
-            stk[lev - 3][tid] = w;
-            mask = w >> kPtrBits;
-            ptr = w & kPtrMask;
-          } else if (lev == k + 2) {
-            const uint32_t w = nodes[ptr + __builtin_popcount(mask & ((1u << oct) - 1u))];
-            bitmap = leaves[w & kPtrMask];
-            mask = leaf_summary(bitmap);
-          } else {
-            mask = (uint32_t)(bitmap >> (8 * oct)) & 0xFFu;
-          }
-          continue;
-        }
-      }
-      // ---- step out of the empty cell c at level lev
-      uint32_t bn = 0, bd = 1, bc = 0, smask = 0;
-      for (int a = 0; a < 3; a++) {
-        if (!dsg[a]) continue;
-        const int64_t X = (int64_t)(dsg[a] > 0 ? c[a] + 1 : c[a]) << (lev + 16);
-        const uint32_t n = (uint32_t)(dsg[a] > 0 ? X - p.O[a] : p.O[a] - X);
-        const uint32_t cls = dsg[a] < 0;
-        if (!smask) { bn = n; bd = ad[a]; bc = cls; smask = 1u << a; continue; }
-        const uint64_t l = (uint64_t)n * bd, r = (uint64_t)bn * ad[a];
-        if (l < r || (l == r && cls < bc)) { bn = n; bd = ad[a]; bc = cls; smask = 1u << a; }
-        else if (l == r && cls == bc) smask |= 1u << a;
-      }
-      if (!smask) break;  // D == 0: the ray never leaves this cell
-      Nt = bn; Dt = bd; ph = bc;
-      uint32_t diff = 0;
-      for (int a = 0; a < 3; a++) {
-        if (!((smask >> a) & 1)) continue;
-        const int32_t nc = c[a] + dsg[a];
-        diff |= (uint32_t)(nc ^ c[a]);
-        c[a] = nc;
-      }
-      const int pl = lev + (32 - __builtin_clz(diff));  // lowest common ancestor level
-      if (pl > CL) {
-        for (int a = 0; a < 3; a++) c[a] >>= (CL - lev);
-        lev = CL;
-        at_chunk = true;
-        continue;
-      }
-      for (int a = 0; a < 3; a++) c[a] >>= (pl - lev);
-      lev = pl;
-      if (lev >= k + 3) {
-        const uint32_t w = stk[lev - 3][tid];
-        mask = w >> kPtrBits;
-        ptr = w & kPtrMask;
-      } else if (lev == k + 2) {
-        mask = leaf_summary(bitmap);
-      } else {
-        const uint32_t o1 = (c[0] & 1) | ((c[1] & 1) << 1) | ((c[2] & 1) << 2);
-        mask = (uint32_t)(bitmap >> (8 * o1)) & 0xFFu;
-      }
-    }
-  }
-  reinterpret_cast<uint4*>(p.out)[(size_t)py * p.W + px] = rec;
+  reinterpret_cast<uint4*>(p.out)[(size_t)py * p.W + px] = trace_pixel(p, px, py, &stk[0][tid], kBlock);
 }
 
 int launch_trace(const TraceParams& p, void* stream) {

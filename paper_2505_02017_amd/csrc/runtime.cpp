@@ -302,7 +302,7 @@ typedef __int128 i128;
 // rays (pixel-centre rays of the image corners).  Every pixel direction is a
 // convex combination of the corners.  Returns false when the cone is
 // degenerate; then culling is disabled for the view.
-static bool cull_planes(const svd_ray_frame* f, int64_t n[4][3]) {
+bool svd::cull_planes(const svd_ray_frame* f, int64_t n[4][3]) {
   int64_t C[4][3];
   const int64_t W1 = (int64_t)f->width - 1, H1 = (int64_t)f->height - 1;
   const int64_t px[4] = {0, W1, W1, 0}, py[4] = {0, 0, H1, H1};

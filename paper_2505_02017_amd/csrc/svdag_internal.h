@@ -87,6 +87,9 @@ struct StageParams {
   uint32_t* view;
 };
 
+// runtime.cpp: inward normals of the view cone's side planes (false = degenerate)
+bool cull_planes(const svd_ray_frame* f, int64_t n[4][3]);
+
 // kernels.hip
 int launch_chunk_stage(const StageParams& p, void* stream);
 int launch_trace(const TraceParams& p, void* stream);
