@@ -471,7 +471,11 @@ int derive_device(LodData& L, std::vector<uint8_t>& image) {
       const uint32_t p = L.words[s + 2 + j];
       uint32_t cw, cc;
       if (lev == 3) {
-        cw = p;
+        // a leaf's "mask" is its 8-bit summary: bit i set iff 2^3 sub-block i is non-empty
+        uint32_t summary = 0;
+        for (int s = 0; s < 8; s++)
+          if ((L.leaves[p] >> (8 * s)) & 0xFFu) summary |= 1u << s;
+        cw = (summary << kPtrBits) | p;
         cc = (uint32_t)__builtin_popcountll(L.leaves[p]);
       } else {
         level_of[p] = lev - 1;

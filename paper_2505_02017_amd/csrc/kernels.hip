@@ -9,10 +9,13 @@
 // Each ray is mirrored on the axes where D < 0 (as ESVO does), so that every
 // direction component is >= 0 and every cell coordinate only grows; a
 // mirrored axis keeps class 1 (its cells are closed at their upper plane).
-// Then "the ray is past plane X of axis a" is the single key comparison
-// ((X - O_a) / |D_a|, class_a) <= (Nt / Dt, phase), one 32x32->64-bit
-// multiply against R_a = Nt |D_a|, which is recomputed once per step.  No
-// division anywhere in the kernel.
+// A plane of axis a at numerator N = X - O_a (fixed point) is crossed at the
+// key (N / |D_a|, class_a); it is behind the current instant iff
+//     N * 2 Dt  <  T_a = 2 Nt |D_a| + 1 + phase - class_a,
+// one 32x32->64-bit multiply-add per test, T_a being refreshed once per
+// step.  The exit planes of the current cell are kept as numerators E_a:
+// a mid-plane is E_a - half a cell, a child's exits are E_a or the mid-plane,
+// a step adds one cell.  No division anywhere in the kernel.
 //
 // The walk is one hierarchy: chunk grid (level chunk_log2, in voxels), the
 // chunk's DAG levels down to 8^3 nodes (level k+3 for LOD k), the 4^3 leaf
@@ -111,40 +114,45 @@ constexpr uint32_t kFaultChunk = 0xFFFFFFFEu;
 
 enum : uint32_t { kRunning = 0, kHit = 1, kMiss = 2, kFault = 3 };
 
-// 8-bit mask of the non-empty bytes of a leaf bitmap (= non-empty 2^3 sub-blocks).
 __host__ __device__ __forceinline__ uint32_t float_bits(float f) {
   union { float f; uint32_t u; } v;
   v.f = f;
   return v.u;
 }
 
-__host__ __device__ __forceinline__ uint32_t leaf_summary(uint64_t b) {
-  b |= b >> 4;
-  b |= b >> 2;
-  b |= b >> 1;
-  b &= 0x0101010101010101ull;
-  return (uint32_t)((b * 0x0102040810204080ull) >> 56);
-}
+// DAG arrays live in global memory (the world's pool); naming the address
+// space lets the loads be global_load rather than flat_load.
+#define SVD_GLOBAL __attribute__((address_space(1)))
+typedef const SVD_GLOBAL uint32_t* gptr32;
+typedef const SVD_GLOBAL uint64_t* gptr64;
+typedef const SVD_GLOBAL uint8_t* gptr8;
 
 // Ray in mirrored coordinates and its current instant.
 struct Ray {
-  int64_t Om[3];   // mirrored origin, voxels * 2^16
-  uint32_t ad[3];  // |D_a|
-  uint32_t mm;     // mirror mask (bit a: D_a < 0) = class bits
-  uint32_t Nt, Dt, ph;
-  uint64_t R[3];   // Nt * ad[a]
+  int64_t Om[3];    // mirrored origin, voxels * 2^16
+  uint32_t Oml[3];  // low 32 bits of Om: plane numerators in [0, 2^32) are exact mod 2^32
+  uint32_t ad[3];   // |D_a|
+  uint32_t ad2[3];  // 2 |D_a| (< 2^32)
+  uint32_t mm;      // mirror mask (bit a: D_a < 0) = class bits
+  uint32_t Nt, Dt, ph, D2;
+  uint64_t T[3];    // 2 Nt |D_a| + 1 + ph - class_a
 
-  // Has the current instant passed plane X16 (mirrored, voxels*2^16) of axis a?
+  __host__ __device__ __forceinline__ uint32_t cls(int a) const { return (mm >> a) & 1u; }
+  // Is the plane of axis a with numerator N >= 0 behind the current instant?
+  __host__ __device__ __forceinline__ bool past_n(int a, uint32_t N) const {
+    return (uint64_t)N * D2 < T[a];
+  }
+  // Same for a plane given in mirrored fixed point (possibly behind the origin).
   __host__ __device__ __forceinline__ bool past(int a, int64_t X16) const {
     const int64_t N = X16 - Om[a];
-    const uint64_t L = (uint64_t)(uint32_t)N * Dt;
-    return N < 0 || L < R[a] || (L == R[a] && ((mm >> a) & 1u) <= ph);
+    return (N < 0) | past_n(a, (uint32_t)N);
   }
-  __host__ __device__ __forceinline__ void set_time(uint32_t n, uint32_t d, uint32_t cls) {
+  __host__ __device__ __forceinline__ void set_time(uint32_t n, uint32_t d, uint32_t c) {
     Nt = n;
     Dt = d;
-    ph = cls;
-    _Pragma("unroll") for (int a = 0; a < 3; a++) R[a] = (uint64_t)Nt * ad[a];
+    ph = c;
+    D2 = 2u * d;
+    _Pragma("unroll") for (int a = 0; a < 3; a++) T[a] = (uint64_t)n * ad2[a] + (1u + c - cls(a));
   }
 };
 
@@ -160,9 +168,11 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
   _Pragma("unroll") for (int a = 0; a < 3; a++) {
     D[a] = (int32_t)(p.A[a] + (int64_t)px * p.BX[a] + (int64_t)py * p.BY[a]);
     r.ad[a] = (uint32_t)(D[a] < 0 ? -(int64_t)D[a] : (int64_t)D[a]);
+    r.ad2[a] = 2u * r.ad[a];
     const int64_t ext16 = (int64_t)p.grid[a] << (CL + 16);
     if (D[a] < 0) r.mm |= 1u << a;
     r.Om[a] = D[a] < 0 ? ext16 - p.O[a] : p.O[a];
+    r.Oml[a] = (uint32_t)r.Om[a];
   }
 
   // World entry: the latest lower bound of the per-axis slabs (mirrored
@@ -171,14 +181,15 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
   _Pragma("unroll") for (int a = 0; a < 3; a++) {
     // a class-1 axis starting exactly on plane 0 still enters just after t = 0
     if (r.Om[a] > 0 || r.ad[a] == 0) continue;
-    const uint32_t n = (uint32_t)(-r.Om[a]), cls = (r.mm >> a) & 1u;
+    const uint32_t n = (uint32_t)(-r.Om[a]), cl = r.cls(a);
     const uint64_t l = (uint64_t)n * d0, q = (uint64_t)n0 * r.ad[a];
-    if (l > q || (l == q && cls > c0)) { n0 = n; d0 = r.ad[a]; c0 = cls; }
+    if (l > q || (l == q && cl > c0)) { n0 = n; d0 = r.ad[a]; c0 = cl; }
   }
   r.set_time(n0, d0, c0);
 
   uint32_t status = kRunning;
   int32_t c[3];
+  uint32_t E[3];  // exit-plane numerators of cell c at level lev
   _Pragma("unroll") for (int a = 0; a < 3; a++) {
     const int64_t ext16 = (int64_t)p.grid[a] << (CL + 16);
     if (!r.past(a, 0) || r.past(a, ext16)) status = kMiss;
@@ -189,14 +200,15 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
       if (r.past(a, (int64_t)mid << (CL + 16))) lo = mid; else hi = mid;
     }
     c[a] = (int32_t)lo;
+    E[a] = ((lo + 1) << (CL + 16)) - r.Oml[a];
   }
 
   int lev = CL, k = 0;
   bool at_chunk = true;
-  uint32_t mask = 0, ptr = 0, ci = 0, iter = 0;
+  uint32_t mask = 0, lmask = 0, ptr = 0, ci = 0, iter = 0;
   uint64_t bitmap = 0;
-  const uint32_t* nodes = nullptr;
-  const uint64_t* leaves = nullptr;
+  gptr32 nodes = nullptr;
+  gptr64 leaves = nullptr;
   while (status == kRunning) {
     if (++iter > kMaxIter) { status = kFault; break; }
     bool step = false;
@@ -206,7 +218,7 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
         break;
       }
       uint32_t co[3];
-      _Pragma("unroll") for (int a = 0; a < 3; a++) co[a] = ((r.mm >> a) & 1u) ? p.grid[a] - 1 - (uint32_t)c[a] : (uint32_t)c[a];
+      _Pragma("unroll") for (int a = 0; a < 3; a++) co[a] = r.cls(a) ? p.grid[a] - 1 - (uint32_t)c[a] : (uint32_t)c[a];
       ci = co[0] + p.grid[0] * (co[1] + p.grid[1] * co[2]);
       const uint32_t v = p.view[ci];
       if (v & (kViewCulled | kViewEmpty)) {
@@ -214,8 +226,8 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
       } else {
         k = (int)(v & kViewLodMask);
         const DevDag* dag = &p.desc[(size_t)ci * 4 + k];
-        nodes = (const uint32_t*)dag->nodes;
-        leaves = (const uint64_t*)dag->leaves;
+        nodes = (gptr32)dag->nodes;
+        leaves = (gptr64)dag->leaves;
         const uint32_t root = dag->root;
         stk[(CL - 3) * ss] = root;
         mask = root >> kPtrBits;
@@ -225,64 +237,74 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
     }
     if (!step) {
       // descend: the child of cell c (level lev) holding the current instant
+      const uint32_t half = 1u << (lev - 1 + 16);
       uint32_t bits = 0;
       _Pragma("unroll") for (int a = 0; a < 3; a++) {
-        const uint32_t b = r.past(a, (int64_t)(2 * c[a] + 1) << (lev - 1 + 16)) ? 1u : 0u;
+        const uint32_t nm = E[a] - half;  // mid-plane numerator
+        const uint32_t b = (uint32_t)(E[a] < half) | (uint32_t)r.past_n(a, nm);
         c[a] = 2 * c[a] + (int32_t)b;
+        E[a] = b ? E[a] : nm;
         bits |= b << a;
       }
       lev--;
       const uint32_t oct = bits ^ r.mm;  // octant in the unmirrored node
       if ((mask >> oct) & 1u) {
         if (lev == k) { status = kHit; break; }
-        if (lev >= k + 3) {
+        if (lev >= k + 2) {
           const uint32_t w = nodes[ptr + __builtin_popcount(mask & ((1u << oct) - 1u))];
-          stk[(lev - 3) * ss] = w;
           mask = w >> kPtrBits;
           ptr = w & kPtrMask;
-        } else if (lev == k + 2) {
-          const uint32_t w = nodes[ptr + __builtin_popcount(mask & ((1u << oct) - 1u))];
-          bitmap = leaves[w & kPtrMask];
-          mask = leaf_summary(bitmap);
+          if (lev >= k + 3) {
+            stk[(lev - 3) * ss] = w;
+          } else {  // a leaf: its word carries the sub-block summary
+            lmask = mask;
+            bitmap = leaves[ptr];
+          }
         } else {
           mask = (uint32_t)(bitmap >> (8 * oct)) & 0xFFu;
         }
         continue;
       }
     }
-    // ---- step out of the empty cell c at level lev: earliest exit plane
-    uint32_t bn = 0, bd = 0, bc = 0, sm = 0;
-    _Pragma("unroll") for (int a = 0; a < 3; a++) {
-      const uint32_t n = (uint32_t)((((int64_t)c[a] + 1) << (lev + 16)) - r.Om[a]);
-      const uint32_t cls = (r.mm >> a) & 1u;
-      if (a == 0) { bn = n; bd = r.ad[0]; bc = cls; sm = 1u; continue; }
-      const uint64_t l = (uint64_t)n * bd, q = (uint64_t)bn * r.ad[a];
-      if (l < q || (l == q && cls < bc)) { bn = n; bd = r.ad[a]; bc = cls; sm = 1u << a; }
-      else if (l == q && cls == bc) sm |= 1u << a;
+    // ---- step out of the empty cell c at level lev: earliest exit plane.
+    // Key of axis a, scaled against axis b: E_a * 2|D_b| + class_a.
+    uint32_t bE = E[0], bA = r.ad[0], bA2 = r.ad2[0], bC = r.cls(0), sm = 1u;
+    _Pragma("unroll") for (int a = 1; a < 3; a++) {
+      const uint64_t ka = (uint64_t)E[a] * bA2 + r.cls(a);
+      const uint64_t kb = (uint64_t)bE * r.ad2[a] + bC;
+      const bool lt = ka < kb, eq = ka == kb;
+      bE = lt ? E[a] : bE;
+      bA = lt ? r.ad[a] : bA;
+      bA2 = lt ? r.ad2[a] : bA2;
+      bC = lt ? r.cls(a) : bC;
+      sm = lt ? (1u << a) : (eq ? sm | (1u << a) : sm);
     }
-    if (bd == 0) { status = kMiss; break; }  // D == 0: the ray never leaves this cell
-    r.set_time(bn, bd, bc);
+    if (bA == 0) { status = kMiss; break; }  // D == 0: the ray never leaves this cell
+    r.set_time(bE, bA, bC);
     uint32_t diff = 0;
     _Pragma("unroll") for (int a = 0; a < 3; a++) {
-      if (!((sm >> a) & 1u)) continue;
-      diff |= (uint32_t)(c[a] ^ (c[a] + 1));
-      c[a] += 1;
+      const uint32_t s = (sm >> a) & 1u;
+      diff |= (uint32_t)(c[a] ^ (c[a] + (int32_t)s));
+      c[a] += (int32_t)s;
     }
-    const int pl = lev + (32 - __builtin_clz(diff));  // lowest common ancestor level
+    int pl = lev + (32 - __builtin_clz(diff));  // lowest common ancestor level
     if (pl > CL) {
-      _Pragma("unroll") for (int a = 0; a < 3; a++) c[a] >>= (CL - lev);
-      lev = CL;
+      pl = CL;
       at_chunk = true;
-      continue;
     }
-    _Pragma("unroll") for (int a = 0; a < 3; a++) c[a] >>= (pl - lev);
+    // exit planes of the ancestor cell (numerators in [0, 2^32) inside the world)
+    _Pragma("unroll") for (int a = 0; a < 3; a++) {
+      c[a] >>= (pl - lev);
+      E[a] = ((uint32_t)(c[a] + 1) << (pl + 16)) - r.Oml[a];
+    }
     lev = pl;
+    if (at_chunk) continue;
     if (lev >= k + 3) {
       const uint32_t w = stk[(lev - 3) * ss];
       mask = w >> kPtrBits;
       ptr = w & kPtrMask;
     } else if (lev == k + 2) {
-      mask = leaf_summary(bitmap);
+      mask = lmask;
     } else {
       const uint32_t o1 = (((uint32_t)c[0] & 1u) | (((uint32_t)c[1] & 1u) << 1) | (((uint32_t)c[2] & 1u) << 2)) ^ r.mm;
       mask = (uint32_t)(bitmap >> (8 * o1)) & 0xFFu;
@@ -295,10 +317,10 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
     // unmirrored LOD-k cell
     int32_t h[3];
     _Pragma("unroll") for (int a = 0; a < 3; a++)
-      h[a] = ((r.mm >> a) & 1u) ? (int32_t)((p.grid[a] << (CL - k)) - 1) - c[a] : c[a];
+      h[a] = r.cls(a) ? (int32_t)((p.grid[a] << (CL - k)) - 1) - c[a] : c[a];
     const DevDag* dag = &p.desc[(size_t)ci * 4 + k];
     // DFS index (Section 3.3): counts of earlier siblings along the path
-    const uint32_t* pre = (const uint32_t*)dag->pre;
+    const gptr32 pre = (gptr32)dag->pre;
     uint32_t dfs = 0;
     for (int L = CL; L >= k + 3; L--) {
       const uint32_t w = stk[(L - 3) * ss];
@@ -310,21 +332,21 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
     const uint32_t o0 = (h[0] & 1) | ((h[1] & 1) << 1) | ((h[2] & 1) << 2);
     dfs += (uint32_t)__builtin_popcountll(bitmap & ((1ull << (8 * o1 + o0)) - 1ull));
     // material: the last run starting at or before the DFS index
-    const uint32_t* rs = (const uint32_t*)dag->rle_start;
+    const gptr32 rs = (gptr32)dag->rle_start;
     uint32_t lo = 0, hi = dag->rle_n;
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
       if (rs[mid] <= dfs) lo = mid; else hi = mid;
     }
-    const uint32_t mat = ((const uint8_t*)dag->rle_mat)[lo];
+    const uint32_t mat = ((gptr8)dag->rle_mat)[lo];
     // entry face: lowest axis whose entry plane is crossed at the hit instant
     uint32_t face = 0;
     _Pragma("unroll") for (int a = 0; a < 3; a++) {
       if (face || !D[a]) continue;
-      const uint32_t cls = (r.mm >> a) & 1u;
-      const int64_t X16 = (int64_t)(cls ? h[a] + 1 : h[a]) << (k + 16);
-      const int64_t ne = cls ? p.O[a] - X16 : X16 - p.O[a];
-      if (ne >= 0 && cls == r.ph && (uint64_t)ne * r.Dt == (uint64_t)r.Nt * r.ad[a]) face = 1 + 2 * a + cls;
+      const uint32_t cl = r.cls(a);
+      const int64_t X16 = (int64_t)(cl ? h[a] + 1 : h[a]) << (k + 16);
+      const int64_t ne = cl ? p.O[a] - X16 : X16 - p.O[a];
+      if (ne >= 0 && cl == r.ph && (uint64_t)ne * r.Dt == (uint64_t)r.Nt * r.ad[a]) face = 1 + 2 * a + cl;
     }
     const double len = sqrt((double)D[0] * D[0] + (double)D[1] * D[1] + (double)D[2] * D[2]);
     const float t = (float)(((double)r.Nt / (double)r.Dt) * len * (1.0 / 65536.0));

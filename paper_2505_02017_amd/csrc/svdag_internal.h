@@ -16,8 +16,9 @@ namespace svd {
 // 3.2): a node with k children is k consecutive u32 "child words",
 // child word = (mask of the child << 24) | pointer, in ascending octant.
 // The pointer of an internal child is the child's word offset; for the
-// children of a level-3 node it indexes the u64 leaf bitmaps.  Keeping the
-// child's mask in its parent makes every descent one 4-byte load.  A parallel
+// children of a level-3 node it indexes the u64 leaf bitmaps, and the "mask"
+// is the leaf's 8-bit summary (bit i: 2^3 sub-block i is non-empty).  Keeping
+// the child's mask in its parent makes every descent one 4-byte load.  A parallel
 // u32 array `pre` holds, at the same offsets, the solid count of the earlier
 // siblings (the DFS prefix of Section 3.3), read only once per hit.
 struct alignas(64) DevDag {
