@@ -46,6 +46,26 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def counter_profile(workload):
+    """Counter-derived figures of the trace kernel from the committed profile
+    (profiles/trace_kernel_<workload>_traffic.txt), or {} if that profile was
+    taken on a different kernel source than the one built here."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"trace_kernel_{workload}_traffic.txt")
+    src = os.path.join(ROOT, "paper_2505_02017_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return {}
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.split()[0] if v.split() else ""
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if vals.get("kernel_source_sha256_16") != sha:
+        return {}
+    return vals
+
+
 def bytes_per_ray(counts, hits, lods, chunk_log2, n_rle):
     """Algorithmic bytes of the trace kernel for each ray:
     4 B view entry per chunk visited; 20 B per chunk DAG entered (node and
@@ -229,12 +249,22 @@ def main():
         launches = np.bincount(np.arange(args.steps) % nviews, minlength=nviews)
         bytes_per_launch = float((view_b * launches).sum() / launches.sum()) * W * H
         achieved = bytes_per_launch / (trace_ms.mean() * 1e-3) / 1e9
+        prof = counter_profile(args.workload)
+        traffic = float(prof["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in prof else None
         result["roofline"] = {
             "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": round(traffic) if traffic is not None else None,
             "kernel": "trace_kernel", "bytes_per_ray": round(mean_b, 2),
             "bytes_per_launch": round(bytes_per_launch), "launch_ms": round(float(trace_ms.mean()), 4),
         }
+        if "valu_insts_per_launch" in prof:
+            # VALU issue view: wave instructions per second over the issue peak
+            # (1024 SIMDs x 2.4 GHz / 4 cycles per wave64 VALU instruction)
+            rate = float(prof["valu_insts_per_launch"]) / (trace_ms.mean() * 1e-3)
+            peak = 1024 * 2.4e9 / 4
+            result["valu_issue"] = {"achieved": round(rate / 1e9, 2), "peak": round(peak / 1e9, 2),
+                                    "unit": "G wave-instructions/s", "frac": round(rate / peak, 4)}
         # ---- CPU baseline: the oracle (as is) on a bounded sample: whole views
         #      in benchmark order while the time budget lasts, else evenly
         #      spaced pixels of view 0
