@@ -95,6 +95,9 @@ def main():
                     help="skip the oracle legs (CPU baseline and visit counts)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-baseline time")
     ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--batch-views", type=int, default=64,
+                    help="views in the batched-launch comparison (0 = skip it)")
+    ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -169,8 +172,8 @@ def main():
     desc = svdag.make_desc(CL, sw.grid, lod_count, thr)
     dev_bytes = sum(svdag.svd_blob_stats_get(b, k)["device_bytes"] for b in blobs.values()
                     for k in range(lod_count))
-    pool = torch.empty(svdag.table_bytes(sw.grid) + dev_bytes + 256 * nch, dtype=torch.uint8,
-                       device="cuda")
+    pool = torch.empty(svdag.table_bytes(sw.grid) + dev_bytes + 256 * nch + (8 << 20),
+                       dtype=torch.uint8, device="cuda")
     world = svdag.svd_world_create(desc, pool)
     for ci, b in blobs.items():
         svdag.svd_chunk_upload(world, (ci % gx, (ci // gx) % gy, ci // (gx * gy)), b)
@@ -298,7 +301,71 @@ def main():
                       f"{args.threads} threads, {dt:.1f}s",
         }
 
+    if args.batch_views > 0:
+        result["batched"] = bench_batched(args, sw, world, svdag, torch)
+
     print(json.dumps(result), flush=True)
+
+
+def bench_batched(args, sw, world, svdag, torch):
+    """A batch of views of mixed resolution over the same world: one
+    graph-launched batch (autotuned tiling) against per-view launches."""
+    rng = np.random.default_rng([args.seed, 64])
+    sizes = [(320, 180), (640, 360), (1280, 720), (1920, 1080)]
+    cams = []
+    for i in range(args.batch_views):
+        W, H = sizes[int(rng.integers(0, len(sizes)))]
+        cams.append(sw.views(1, 1000 + i, W, H)[0])
+    nrec = svdag.batch_records(cams)
+    frames = [svdag.svd_camera_frame(c) for c in cams]
+    offs = np.concatenate([[0], np.cumsum([c.width * c.height for c in cams])])
+    out_b = torch.empty((nrec, 4), dtype=torch.int32, device="cuda")
+    out_p = torch.empty((nrec, 4), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    batch = svdag.svd_batch_create(world, len(cams))
+    tw, claim, occ, _ = svdag.svd_batch_tune(batch, cams, out_b, reps=3, stream=stream)
+    log(f"batch of {len(cams)} views ({nrec} rays): tuned tile {tw}x{64 // tw}, claim {claim}, "
+        f"{occ} blocks/CU")
+
+    def plain():
+        for v, f in enumerate(frames):
+            svdag.svd_trace_frame(world, f, out_p[offs[v]:offs[v + 1]], 0, stream)
+
+    def batched():
+        svdag.svd_batch_trace_frames(batch, frames, out_b, 0, stream)
+
+    res = {}
+    for name, fn in (("plain", plain), ("batched", batched)):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.batch_reps)]
+        t0 = time.perf_counter()
+        for e in ev:
+            e[0].record(stream)
+            fn()
+            e[1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = np.array([e[0].elapsed_time(e[1]) for e in ev])
+        res[name] = (wall, ms)
+    identical = bool(torch.equal(out_b, out_p))
+    svdag.svd_batch_destroy(batch)
+    wb, mb = res["batched"]
+    wp, mp = res["plain"]
+    return {
+        "views": len(cams), "rays_per_batch": int(nrec), "resolutions": "uniform over 320x180, 640x360, "
+        "1280x720, 1920x1080", "tile": f"{tw}x{64 // tw}", "claim": claim,
+        "blocks_per_cu": occ,
+        "batched_grays": round(nrec * args.batch_reps / wb / 1e9, 4),
+        "plain_grays": round(nrec * args.batch_reps / wp / 1e9, 4),
+        "speedup": round(wp / wb, 3),
+        "batched_ms_p50": round(float(np.percentile(mb, 50)), 4),
+        "batched_ms_p99": round(float(np.percentile(mb, 99)), 4),
+        "plain_ms_p50": round(float(np.percentile(mp, 50)), 4),
+        "plain_ms_p99": round(float(np.percentile(mp, 99)), 4),
+        "identical_to_plain": identical,
+    }
 
 
 if __name__ == "__main__":

@@ -160,8 +160,9 @@ typedef struct svd_world svd_world;
 
 /* pool_dev: caller-owned device buffer (e.g. a torch uint8 tensor), 256-byte
  * aligned, that must outlive the world; the library only sub-allocates it.
- * The world's tables take (nchunks * 4 * 64 + nchunks * 4) bytes at its
- * start.  Errors: SVD_EINVAL, SVD_ENOMEM (pool too small for the tables). */
+ * The world's tables take nchunks*4*64 + round256(nchunks*4) + 256 bytes at
+ * its start.  Must be called with the pool's device current.  Errors:
+ * SVD_EINVAL, SVD_ENOMEM (pool too small for the tables), SVD_EDEVICE. */
 int svd_world_create(const svd_world_desc* desc, void* pool_dev, size_t pool_bytes,
                      svd_world** out);
 void svd_world_destroy(svd_world* w);
@@ -209,9 +210,62 @@ int svd_trace_frame(svd_world* w, const svd_ray_frame* frame, svd_hit* out_dev, 
 int svd_view_stage(svd_world* w, const svd_ray_frame* frame, uint32_t flags, void* stream);
 int svd_view_trace(svd_world* w, const svd_ray_frame* frame, svd_hit* out_dev, void* stream);
 
+/* Occupancy of the per-view persistent trace: the grid is blocks_per_cu x
+ * (compute units) blocks of 4 waves, but never more waves than the view has
+ * 64-pixel tiles.  0 selects the default, 4 blocks per CU (or the most that
+ * fit, if fewer); more than fit is SVD_EINVAL.  Results do not depend on it. */
+int svd_world_set_occupancy(svd_world* w, uint32_t blocks_per_cu);
+int svd_world_get_occupancy(const svd_world* w, uint32_t* blocks_per_cu, uint32_t* max_per_cu);
+
 /* Per-chunk LOD (bits 0-1), culled (bit 2) and empty (bit 3) flags of the
  * last traced view, copied to host (synchronises `stream`). */
 int svd_view_table(svd_world* w, uint32_t* out, uint32_t n, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batches of views: many cameras of uneven resolution traced in one graph
+ * launch (a per-(view, chunk) chunk stage and one persistent trace whose
+ * waves take 64-pixel tiles of any view from a shared work queue).  Each
+ * view's records are identical to what svd_trace_view writes for it alone.
+ * ------------------------------------------------------------------------ */
+typedef struct svd_batch svd_batch;
+
+/* Takes 256 + 256*max_views + 4*max_views*nchunks bytes (rounded to 256)
+ * from the world's pool and captures the batch's graph.  The batch must be
+ * destroyed before its world.  Errors: SVD_EINVAL (max_views 1..65535),
+ * SVD_ENOMEM (pool), SVD_EDEVICE. */
+int svd_batch_create(svd_world* w, uint32_t max_views, svd_batch** out);
+void svd_batch_destroy(svd_batch* b);
+
+/* Trace n <= max_views cameras.  Records of view v start at the sum of the
+ * pixel counts of views 0..v-1 in out_dev (row-major per view); out_records
+ * is the capacity of out_dev.  Enqueue-only on `stream`.  The camera array
+ * is read during the call only.  Errors as svd_trace_view, plus SVD_EINVAL
+ * when the views need more than out_records records. */
+int svd_batch_trace(svd_batch* b, const svd_camera* cams, uint32_t n, svd_hit* out_dev,
+                    uint64_t out_records, uint32_t flags, void* stream);
+int svd_batch_trace_frames(svd_batch* b, const svd_ray_frame* frames, uint32_t n, svd_hit* out_dev,
+                           uint64_t out_records, uint32_t flags, void* stream);
+
+/* Work shape of the persistent trace: a wave's tile is tile_w x (64/tile_w)
+ * pixels (tile_w in {8, 16, 32, 64}); a wave takes `claim` (1..16)
+ * consecutive tiles per queue access.  Results do not depend on it. */
+int svd_batch_set_tiling(svd_batch* b, uint32_t tile_w, uint32_t claim);
+
+/* Persistent grid of the batch trace: blocks_per_cu x (compute units) blocks
+ * of 4 waves; 0 selects the most that fit a CU (the default), more is
+ * SVD_EINVAL.  A change re-captures the batch's graph, after waiting for the
+ * batch's last launch to finish.  Results do not depend on it. */
+int svd_batch_set_occupancy(svd_batch* b, uint32_t blocks_per_cu);
+int svd_batch_get_tiling(const svd_batch* b, uint32_t* tile_w, uint32_t* claim, uint32_t* blocks_per_cu);
+
+/* Autotuner: times every tiling candidate (tile width 8/16/32 x claim
+ * 1/2/4) at the current occupancy, then every occupancy from the maximum
+ * down to 2 blocks per CU at the best tiling, on this batch of cameras
+ * (median of `reps` launches after one warm-up, HIP events on `stream`;
+ * synchronises it); keeps the fastest and returns its time in *best_ms
+ * (may be NULL). */
+int svd_batch_tune(svd_batch* b, const svd_camera* cams, uint32_t n, svd_hit* out_dev,
+                   uint64_t out_records, uint32_t reps, void* stream, float* best_ms);
 
 #ifdef __cplusplus
 }

@@ -358,27 +358,135 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
   return rec;
 }
 
+// Persistent: a machine-filling grid whose waves each take 16x4-pixel tiles
+// from a counter until the image is done, so that no wave idles while the
+// slower waves of its work-group finish (ray costs vary widely per tile).
+// queue[0] is the next tile, queue[1] counts waves that found the queue
+// empty; the last of them resets both, so every launch starts from zero.
 __global__ __launch_bounds__(kBlock) void trace_kernel(TraceParams p) {
   __shared__ uint32_t stk[kStackLevels][kBlock];
-  const uint32_t tid = threadIdx.x;
-  // Work-groups are dealt to the 8 XCDs round-robin; give each XCD a
-  // contiguous run of 16x16 pixel blocks so that its L2 sees neighbouring
-  // rays.
-  const uint32_t per_xcd = (p.nblocks + 7) / 8;
-  const uint32_t blk = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (blk >= p.nblocks) return;
-  const uint32_t lane = tid & 63, wv = tid >> 6;
-  const uint32_t px = (blk % p.tiles_x) * 16 + (wv & 1) * 8 + (lane & 7);
-  const uint32_t py = (blk / p.tiles_x) * 16 + (wv >> 1) * 8 + (lane >> 3);
-  if (px >= p.W || py >= p.H) return;
-  reinterpret_cast<uint4*>(p.out)[(size_t)py * p.W + px] = trace_pixel(p, px, py, &stk[0][tid], kBlock);
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
+  constexpr uint32_t tw = kViewTileW, th = 64 / kViewTileW;
+  for (;;) {
+    uint32_t t = 0;
+    if (lane == 0) t = atomicAdd(&p.queue[0], 1u);
+    t = __shfl(t, 0);
+    if (t >= p.total_tiles) {
+      if (lane == 0 && atomicAdd(&p.queue[1], 1u) == gridDim.x * (kBlock / 64) - 1) {
+        atomicExch(&p.queue[0], 0u);
+        atomicExch(&p.queue[1], 0u);
+      }
+      break;
+    }
+    const uint32_t px = (t % p.tiles_x) * tw + lane % tw;
+    const uint32_t py = (t / p.tiles_x) * th + lane / tw;
+    if (px < p.W && py < p.H)
+      reinterpret_cast<uint4*>(p.out)[(size_t)py * p.W + px] = trace_pixel(p, px, py, &stk[0][tid], kBlock);
+  }
 }
 
-int launch_trace(const TraceParams& p, void* stream) {
-  const uint32_t blocks = (p.nblocks + 7) / 8 * 8;
+int trace_occupancy(uint32_t* blocks_per_cu) {
+  int n = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, trace_kernel, kBlock, 0);
+  if (e != hipSuccess || n < 1) return svd_fail(SVD_EDEVICE, "occupancy query failed");
+  *blocks_per_cu = (uint32_t)n;
+  return SVD_OK;
+}
+
+int launch_trace(const TraceParams& p, uint32_t blocks, void* stream) {
   hipLaunchKernelGGL(trace_kernel, dim3(blocks), dim3(kBlock), 0, (hipStream_t)stream, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return svd_fail(SVD_EDEVICE, "trace launch: %s", hipGetErrorString(e));
+  return SVD_OK;
+}
+
+// ----------------------------------------------------------- batched views
+// Many views of uneven size in one pass: a chunk stage over (view, chunk)
+// pairs, then a persistent trace whose waves take 64-pixel tiles of any
+// view from one work queue, so small views fill the machine as well as large
+// ones.  All per-batch values come from device memory (BatchHeader and
+// BatchView), so the three launches are captured once as a graph.
+__global__ void batch_reset_kernel(BatchHeader* hdr) {
+  if (threadIdx.x == 0) hdr->next_tile = 0;
+}
+
+__global__ void batch_stage_kernel(BatchParams p) {
+  const uint32_t v = blockIdx.y;
+  const uint32_t ci = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= p.hdr->nviews || ci >= p.nchunks) return;
+  const BatchView& bv = p.views[v];
+  StageParams sp;
+  _Pragma("unroll") for (int a = 0; a < 3; a++) {
+    sp.O[a] = bv.O[a];
+    sp.grid[a] = p.grid[a];
+    sp.thr[a] = p.thr[a];
+    _Pragma("unroll") for (int i = 0; i < 4; i++) sp.n[i][a] = bv.n[i][a];
+  }
+  sp.chunk_log2 = p.chunk_log2;
+  sp.lod_count = p.lod_count;
+  sp.cull = bv.cull;
+  sp.nchunks = p.nchunks;
+  sp.desc = p.desc;
+  sp.view = nullptr;
+  p.view_tables[(size_t)v * p.nchunks + ci] = stage_chunk(sp, ci);
+}
+
+__global__ __launch_bounds__(kBlock) void batch_trace_kernel(BatchParams p) {
+  __shared__ uint32_t stk[kStackLevels][kBlock];
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
+  const uint32_t total = p.hdr->total_tiles, nviews = p.hdr->nviews;
+  const uint32_t claim = p.hdr->claim, tw = p.hdr->tile_w, th = 64 / tw;
+  svd_hit* out = (svd_hit*)p.hdr->out;
+  for (;;) {
+    // one queue access per wave: lane 0 claims, the wave shares the index
+    uint32_t t0 = 0;
+    if (lane == 0) t0 = atomicAdd(&p.hdr->next_tile, claim);
+    t0 = __shfl(t0, 0);
+    if (t0 >= total) break;
+    const uint32_t t1 = t0 + claim < total ? t0 + claim : total;
+    for (uint32_t t = t0; t < t1; t++) {
+      uint32_t lo = 0, hi = nviews;  // view holding global tile t
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (p.views[mid].tile_base <= t) lo = mid; else hi = mid;
+      }
+      const BatchView& bv = p.views[lo];
+      const uint32_t lt = t - bv.tile_base;
+      const uint32_t px = (lt % bv.tiles_x) * tw + lane % tw;
+      const uint32_t py = (lt / bv.tiles_x) * th + lane / tw;
+      if (px >= bv.W || py >= bv.H) continue;
+      TraceParams tp;
+      _Pragma("unroll") for (int a = 0; a < 3; a++) {
+        tp.O[a] = bv.O[a];
+        tp.A[a] = bv.A[a];
+        tp.BX[a] = bv.BX[a];
+        tp.BY[a] = bv.BY[a];
+        tp.grid[a] = p.grid[a];
+      }
+      tp.chunk_log2 = p.chunk_log2;
+      tp.view = p.view_tables + (size_t)lo * p.nchunks;
+      tp.desc = p.desc;
+      reinterpret_cast<uint4*>(out)[bv.out_offset + (size_t)py * bv.W + px] =
+          trace_pixel(tp, px, py, &stk[0][tid], kBlock);
+    }
+  }
+}
+
+int batch_trace_occupancy(uint32_t* blocks_per_cu) {
+  int n = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_trace_kernel, kBlock, 0);
+  if (e != hipSuccess || n < 1) return svd_fail(SVD_EDEVICE, "occupancy query failed");
+  *blocks_per_cu = (uint32_t)n;
+  return SVD_OK;
+}
+
+int launch_batch(const BatchParams& p, uint32_t trace_blocks, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, p.hdr);
+  hipLaunchKernelGGL(batch_stage_kernel, dim3((p.nchunks + 63) / 64, p.max_views), dim3(64), 0, s, p);
+  hipLaunchKernelGGL(batch_trace_kernel, dim3(trace_blocks), dim3(kBlock), 0, s, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return svd_fail(SVD_EDEVICE, "batch launch: %s", hipGetErrorString(e));
   return SVD_OK;
 }
 

@@ -68,12 +68,14 @@ struct TraceParams {
   uint32_t W, H;
   uint32_t grid[3];
   uint32_t chunk_log2;
-  uint32_t tiles_x;       // 16x16-pixel blocks per row
-  uint32_t nblocks;
+  uint32_t tiles_x;       // 16x4-pixel wave tiles per image row
+  uint32_t total_tiles;
+  uint32_t* queue;        // [next tile, waves done]; both zero between launches
   const uint32_t* view;   // per-chunk view entry
   const DevDag* desc;     // [chunk * 4 + lod]
   svd_hit* out;
 };
+constexpr uint32_t kViewTileW = 16;  // per-view wave tile: 16 x 4 pixels
 
 struct StageParams {
   int64_t O[3];
@@ -88,13 +90,56 @@ struct StageParams {
   uint32_t* view;
 };
 
+// One view of a batch (device memory, 256 bytes).
+struct alignas(256) BatchView {
+  int64_t O[3], A[3], BX[3], BY[3];
+  int64_t n[4][3];        // cull planes (zero = none)
+  uint64_t out_offset;    // first record of this view in the batch output
+  uint32_t W, H;
+  uint32_t tiles_x;       // tiles per image row
+  uint32_t tile_base;     // first global tile index of this view
+  uint32_t cull;
+};
+static_assert(sizeof(BatchView) == 256, "BatchView must stay 256 bytes");
+
+// Batch header (device memory): rewritten by each svd_batch_trace call, so
+// that one captured graph serves every batch.
+struct alignas(64) BatchHeader {
+  uint64_t out;           // device address of the batch's svd_hit records
+  uint32_t nviews;
+  uint32_t total_tiles;
+  uint32_t next_tile;     // work-queue head (reset by a kernel, not a memset)
+  uint32_t tile_w;        // tile width in pixels (tile = tile_w x 64/tile_w)
+  uint32_t claim;         // tiles a wave takes per queue access
+  uint32_t pad[9];
+};
+static_assert(sizeof(BatchHeader) == 64, "BatchHeader must stay 64 bytes");
+
+struct BatchParams {
+  const BatchView* views;
+  BatchHeader* hdr;
+  uint32_t max_views;
+  uint32_t grid[3];
+  uint32_t chunk_log2;
+  uint32_t lod_count;
+  uint32_t thr[3];
+  uint32_t nchunks;
+  const DevDag* desc;
+  uint32_t* view_tables;  // [view * nchunks + chunk]
+};
+
 // runtime.cpp: inward normals of the view cone's side planes (false = degenerate)
 bool cull_planes(const svd_ray_frame* f, int64_t n[4][3]);
+int check_frame(const svd_ray_frame* f);
 
 // kernels.hip
 int launch_chunk_stage(const StageParams& p, void* stream);
-int launch_trace(const TraceParams& p, void* stream);
+int launch_trace(const TraceParams& p, uint32_t blocks, void* stream);
+int trace_occupancy(uint32_t* blocks_per_cu);
 int launch_set_desc(DevDag* dst, const DevDag* src4, uint32_t n, void* stream);
+// batched views: queue reset, per-(view, chunk) stage, persistent trace
+int launch_batch(const BatchParams& p, uint32_t trace_blocks, void* stream);
+int batch_trace_occupancy(uint32_t* blocks_per_cu);
 
 }  // namespace svd
 

@@ -107,6 +107,7 @@ class SceneWorld:
         if not h:
             raise ValueError(f"bad scene kind {kind!r}")
         self._h = h
+        self._free = _lib().sg_world_free  # held: module globals may be gone at exit
         cl = ctypes.c_uint32()
         g = (ctypes.c_uint32 * 3)()
         nb = ctypes.c_int()
@@ -118,7 +119,7 @@ class SceneWorld:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            _lib().sg_world_free(h)
+            self._free(h)
             self._h = None
 
     @property

@@ -34,6 +34,9 @@ EXPORTS = [
     "svd_world_create", "svd_world_destroy", "svd_world_pool_used", "svd_chunk_upload",
     "svd_chunk_evict", "svd_camera_frame", "svd_trace_view", "svd_trace_frame",
     "svd_view_stage", "svd_view_trace", "svd_view_table",
+    "svd_world_set_occupancy", "svd_world_get_occupancy",
+    "svd_batch_create", "svd_batch_destroy", "svd_batch_trace", "svd_batch_trace_frames",
+    "svd_batch_set_tiling", "svd_batch_set_occupancy", "svd_batch_get_tiling", "svd_batch_tune",
 ]
 
 
@@ -102,8 +105,22 @@ def lib() -> ctypes.CDLL:
         L.svd_view_table.argtypes = [vp, ctypes.POINTER(u32), u32, vp]
         L.svd_view_stage.argtypes = [vp, ctypes.POINTER(svd_ray_frame), u32, vp]
         L.svd_view_trace.argtypes = [vp, ctypes.POINTER(svd_ray_frame), vp, vp]
+        L.svd_world_set_occupancy.argtypes = [vp, u32]
+        L.svd_world_get_occupancy.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32)]
+        u64 = ctypes.c_uint64
+        L.svd_batch_create.argtypes = [vp, u32, ctypes.POINTER(vp)]
+        L.svd_batch_destroy.argtypes = [vp]
+        L.svd_batch_destroy.restype = None
+        L.svd_batch_trace.argtypes = [vp, ctypes.POINTER(svd_camera), u32, vp, u64, u32, vp]
+        L.svd_batch_trace_frames.argtypes = [vp, ctypes.POINTER(svd_ray_frame), u32, vp, u64, u32, vp]
+        L.svd_batch_set_tiling.argtypes = [vp, u32, u32]
+        L.svd_batch_set_occupancy.argtypes = [vp, u32]
+        L.svd_batch_get_tiling.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32)]
+        L.svd_batch_tune.argtypes = [vp, ctypes.POINTER(svd_camera), u32, vp, u64, u32, vp,
+                                     ctypes.POINTER(ctypes.c_float)]
         for n in EXPORTS:
-            if n not in ("svd_last_error", "svd_blob_free", "svd_free", "svd_world_destroy"):
+            if n not in ("svd_last_error", "svd_blob_free", "svd_free", "svd_world_destroy",
+                         "svd_batch_destroy"):
                 getattr(L, n).restype = i32
         _lib = L
     return _lib
@@ -134,10 +151,11 @@ class Blob:
 
     def __init__(self, ptr: int):
         self._p = ctypes.c_void_p(ptr)
+        self._free = lib().svd_blob_free  # held: module globals may be gone at exit
 
     def __del__(self):
         if getattr(self, "_p", None) and self._p.value:
-            lib().svd_blob_free(self._p)
+            self._free(self._p)
             self._p = None
 
     @property
@@ -209,7 +227,7 @@ def make_desc(chunk_log2: int, grid, lod_count: int, thresholds=(256, 1024, 4096
 
 def table_bytes(grid) -> int:
     n = int(grid[0]) * int(grid[1]) * int(grid[2])
-    return n * 4 * 64 + (n * 4 + 255) // 256 * 256
+    return n * 4 * 64 + (n * 4 + 255) // 256 * 256 + 256
 
 
 class World:
@@ -222,6 +240,7 @@ class World:
         self.grid = tuple(desc.grid)
         self.nchunks = self.grid[0] * self.grid[1] * self.grid[2]
         self._blobs = {}          # uploaded blobs stay alive until replaced or evicted
+        self._free = lib().svd_world_destroy
 
     @property
     def ptr(self):
@@ -229,7 +248,7 @@ class World:
 
     def __del__(self):
         if getattr(self, "_p", None) and self._p.value:
-            lib().svd_world_destroy(self._p)
+            self._free(self._p)
             self._p = None
 
 
@@ -321,11 +340,111 @@ def svd_view_trace(w: World, frame: svd_ray_frame, out, stream=None):
                                 _stream_ptr(stream)))
 
 
+def svd_world_set_occupancy(w: World, blocks_per_cu: int):
+    _check(lib().svd_world_set_occupancy(w.ptr, blocks_per_cu))
+
+
+def svd_world_get_occupancy(w: World):
+    """(blocks per CU of the per-view trace, the most that fit a CU)."""
+    cur, mx = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().svd_world_get_occupancy(w.ptr, ctypes.byref(cur), ctypes.byref(mx)))
+    return cur.value, mx.value
+
+
 def svd_view_table(w: World, stream=None) -> np.ndarray:
     out = np.zeros(w.nchunks, np.uint32)
     _check(lib().svd_view_table(w.ptr, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
                                 w.nchunks, _stream_ptr(stream)))
     return out
+
+
+# ------------------------------------------------------------------ batches
+
+class Batch:
+    """Views traced together in one graph launch (see svd_batch_create)."""
+
+    def __init__(self, ptr: int, world: World):
+        self._p = ctypes.c_void_p(ptr)
+        self.world = world  # the batch lives in the world's pool
+        self._free = lib().svd_batch_destroy
+
+    @property
+    def ptr(self):
+        return self._p
+
+    def __del__(self):
+        if getattr(self, "_p", None) and self._p.value:
+            self._free(self._p)
+            self._p = None
+
+
+def svd_batch_create(w: World, max_views: int) -> Batch:
+    out = ctypes.c_void_p()
+    _check(lib().svd_batch_create(w.ptr, max_views, ctypes.byref(out)))
+    return Batch(out.value, w)
+
+
+def svd_batch_destroy(b: Batch):
+    if b._p and b._p.value:
+        lib().svd_batch_destroy(b._p)
+        b._p = None
+
+
+def _cam_array(cams):
+    arr = (svd_camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = c if isinstance(c, svd_camera) else to_camera(c)
+    return arr
+
+
+def batch_records(cams) -> int:
+    return sum(int(c.width) * int(c.height) for c in cams)
+
+
+def _batch_out(out):
+    """Device pointer and record capacity of a batch output (the library
+    checks the capacity against the views)."""
+    assert out.is_cuda and out.is_contiguous()
+    return ctypes.c_void_p(out.data_ptr()), out.numel() * out.element_size() // 16
+
+
+def svd_batch_trace(b: Batch, cams, out, flags: int = 0, stream=None):
+    arr = _cam_array(cams)
+    ptr, cap = _batch_out(out)
+    _check(lib().svd_batch_trace(b.ptr, arr, len(cams), ptr, cap, flags, _stream_ptr(stream)))
+
+
+def svd_batch_trace_frames(b: Batch, frames, out, flags: int = 0, stream=None):
+    arr = (svd_ray_frame * len(frames))(*frames)
+    ptr, cap = _batch_out(out)
+    _check(lib().svd_batch_trace_frames(b.ptr, arr, len(frames), ptr, cap, flags, _stream_ptr(stream)))
+
+
+def svd_batch_set_tiling(b: Batch, tile_w: int, claim: int):
+    _check(lib().svd_batch_set_tiling(b.ptr, tile_w, claim))
+
+
+def svd_batch_set_occupancy(b: Batch, blocks_per_cu: int):
+    _check(lib().svd_batch_set_occupancy(b.ptr, blocks_per_cu))
+
+
+def svd_batch_get_tiling(b: Batch):
+    """(tile width, claim, blocks per CU) of the batch trace."""
+    tw, cl, oc = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().svd_batch_get_tiling(b.ptr, ctypes.byref(tw), ctypes.byref(cl), ctypes.byref(oc)))
+    return tw.value, cl.value, oc.value
+
+
+def svd_batch_tune(b: Batch, cams, out, reps: int = 3, stream=None):
+    """Autotune the batch's tiling and occupancy on these cameras; returns
+    (tile_w, claim, blocks_per_cu, ms)."""
+    arr = _cam_array(cams)
+    ptr, cap = _batch_out(out)
+    ms = ctypes.c_float()
+    _check(lib().svd_batch_tune(b.ptr, arr, len(cams), ptr, cap, reps, _stream_ptr(stream),
+                                ctypes.byref(ms)))
+    tw, cl, oc = svd_batch_get_tiling(b)
+    return tw, cl, oc, ms.value
 
 
 # ------------------------------------------------------------------ records

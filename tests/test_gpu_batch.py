@@ -1,0 +1,162 @@
+"""Batched views (one graph launch, persistent trace over a shared tile
+queue): every view's records equal those of its own per-view launch and
+the oracle's, for every tiling, across repeated graph replays."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import build_blobs, compare, gpu_world, note, oracle_world
+from paper_2505_02017_amd import scenes
+
+pytestmark = pytest.mark.gpu
+NT = min(16, os.cpu_count() or 1)
+THR = (48, 96, 160)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_02017_amd import svdag
+    svdag.lib()
+    return svdag, torch
+
+
+@pytest.fixture(scope="module")
+def world(env):
+    svdag, torch = env
+    sw = scenes.SceneWorld("custom", 41, chunk_log2=6, grid=(4, 4, 2))
+    dense = {ci: sw.chunk(c) for ci, c in enumerate(sw.chunks())}
+    note("batch world: 4x4x2 x 64^3, 4 LODs")
+    w = gpu_world(svdag, torch, 6, sw.grid, 4, build_blobs(svdag, 6, 4, dense), THR, extra_bytes=1 << 22)
+    ow = oracle_world(6, sw.grid, 4, dense)
+    return sw, w, ow
+
+
+def _cams(sw, seed, n):
+    rng = np.random.default_rng(seed)
+    sizes = [(1, 1), (7, 5), (64, 48), (33, 17), (160, 90), (96, 96), (250, 3), (2, 130)]
+    cams = []
+    for i in range(n):
+        W, H = sizes[int(rng.integers(0, len(sizes)))]
+        cams.append(sw.views(1, seed * 100 + i, W, H)[0])
+    return cams
+
+
+def _per_view(svdag, torch, w, cams):
+    outs = []
+    for c in cams:
+        o = torch.empty((c.width * c.height, 4), dtype=torch.int32, device="cuda")
+        svdag.svd_trace_view(w, svdag.to_camera(c), o)
+        outs.append(o)
+    torch.cuda.synchronize()
+    return np.concatenate([o.cpu().numpy() for o in outs])
+
+
+def test_batch_equals_per_view_all_tilings(env, world):
+    svdag, torch = env
+    sw, w, ow = world
+    cams = _cams(sw, 1, 12)
+    ref = _per_view(svdag, torch, w, cams)
+    b = svdag.svd_batch_create(w, 16)
+    out = torch.empty((svdag.batch_records(cams), 4), dtype=torch.int32, device="cuda")
+    for tw in (8, 16, 32, 64):
+        for claim in (1, 3):
+            note(f"tiling {tw}x{64 // tw} claim {claim}")
+            svdag.svd_batch_set_tiling(b, tw, claim)
+            out.fill_(-1)
+            svdag.svd_batch_trace(b, cams, out)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), ref), (tw, claim)
+    # and the batch agrees with the oracle view by view
+    raw, off = out.cpu().numpy(), 0
+    for v, c in enumerate(cams):
+        n = c.width * c.height
+        fr = oracle.camera_frame(c)
+        compare(svdag, raw[off:off + n], ow.trace_frame(ow.lod_pick(fr.O, THR), fr, threads=NT),
+                label=f"batch view {v}")
+        off += n
+    svdag.svd_batch_destroy(b)
+
+
+def test_graph_replays_with_changing_batches(env, world):
+    svdag, torch = env
+    sw, w, ow = world
+    b = svdag.svd_batch_create(w, 24)
+    big = torch.empty((24 * 250 * 130, 4), dtype=torch.int32, device="cuda")
+    for rep in range(6):
+        cams = _cams(sw, 10 + rep, 5 + 3 * rep)
+        n = svdag.batch_records(cams)
+        big[:n].fill_(-1)
+        svdag.svd_batch_trace(b, cams, big)
+        # eager work of the program between replays
+        scratch = torch.arange(1 << 16, device="cuda").float().sum()
+        torch.cuda.synchronize()
+        ref = _per_view(svdag, torch, w, cams)
+        assert np.array_equal(big[:n].cpu().numpy(), ref), f"replay {rep}"
+        assert float(scratch) > 0
+    svdag.svd_batch_destroy(b)
+
+
+def test_tuner_and_errors(env, world):
+    svdag, torch = env
+    sw, w, ow = world
+    cams = _cams(sw, 3, 10)
+    b = svdag.svd_batch_create(w, 10)
+    out = torch.empty((svdag.batch_records(cams), 4), dtype=torch.int32, device="cuda")
+    tw, claim, occ, ms = svdag.svd_batch_tune(b, cams, out, reps=2)
+    assert tw in (8, 16, 32) and claim in (1, 2, 4) and occ >= 1 and ms > 0
+    svdag.svd_batch_trace(b, cams, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), _per_view(svdag, torch, w, cams))
+    with pytest.raises(svdag.SvdError) as e:
+        svdag.svd_batch_trace(b, cams + cams[:1], out)          # more views than max_views
+    assert e.value.code == svdag.SVD_EINVAL
+    small = torch.empty((svdag.batch_records(cams) - 1, 4), dtype=torch.int32, device="cuda")
+    with pytest.raises(svdag.SvdError) as e:
+        svdag.svd_batch_trace(b, cams, small)                   # output too small
+    assert e.value.code == svdag.SVD_EINVAL
+    with pytest.raises(svdag.SvdError):
+        svdag.svd_batch_set_tiling(b, 12, 1)
+    with pytest.raises(svdag.SvdError) as e:
+        svdag.svd_batch_set_occupancy(b, 1000)                   # more blocks than fit a CU
+    assert e.value.code == svdag.SVD_EINVAL
+    svdag.svd_batch_destroy(b)
+
+
+def test_occupancy_does_not_change_results(env, world):
+    """The persistent grid size (blocks per CU) of both the batch and the
+    per-view trace changes the schedule only, never a record."""
+    svdag, torch = env
+    sw, w, ow = world
+    cams = _cams(sw, 5, 9)
+    ref = _per_view(svdag, torch, w, cams)
+    b = svdag.svd_batch_create(w, 9)
+    _, _, mx = svdag.svd_batch_get_tiling(b)
+    out = torch.empty((svdag.batch_records(cams), 4), dtype=torch.int32, device="cuda")
+    for occ in sorted({1, 2, mx, 0}):
+        note(f"batch occupancy {occ}")
+        svdag.svd_batch_set_occupancy(b, occ)
+        assert svdag.svd_batch_get_tiling(b)[2] == (occ or mx)
+        for _ in range(2):                                      # two launches of the re-captured graph
+            out.fill_(-1)
+            svdag.svd_batch_trace(b, cams, out)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), ref), occ
+    svdag.svd_batch_destroy(b)
+    cur, wmx = svdag.svd_world_get_occupancy(w)
+    assert cur == min(wmx, 4) and wmx >= 1
+    try:
+        for occ in (1, 2):
+            note(f"per-view occupancy {occ}")
+            svdag.svd_world_set_occupancy(w, occ)
+            assert svdag.svd_world_get_occupancy(w) == (occ, wmx)
+            assert np.array_equal(_per_view(svdag, torch, w, cams), ref), occ
+        with pytest.raises(svdag.SvdError) as e:
+            svdag.svd_world_set_occupancy(w, wmx + 1)
+        assert e.value.code == svdag.SVD_EINVAL
+    finally:
+        svdag.svd_world_set_occupancy(w, 0)

@@ -157,6 +157,29 @@ def test_ragged_and_tiny_images(env, terrain):
         compare(svdag, raw, ref, label=f"{W}x{H}")
 
 
+def test_stage_once_trace_repeatedly(env, terrain):
+    """The persistent trace leaves its work queue at zero: tracing one staged
+    view several times gives the same records every time; a trace whose
+    frame differs from the staged one is refused."""
+    svdag, torch = env
+    sw, w, ow, thr = terrain
+    cams = sw.views(2, 77, 97, 61)
+    f0, f1 = (svdag.svd_camera_frame(c) for c in cams)
+    outs = [torch.full((97 * 61, 4), -1, dtype=torch.int32, device="cuda") for _ in range(3)]
+    svdag.svd_view_stage(w, f0)
+    for o in outs:
+        svdag.svd_view_trace(w, f0, o)
+    torch.cuda.synchronize()
+    ref = outs[0].cpu().numpy()
+    for o in outs[1:]:
+        assert np.array_equal(o.cpu().numpy(), ref)
+    fr = oracle.camera_frame(cams[0])
+    compare(svdag, ref, ow.trace_frame(ow.lod_pick(fr.O, thr), fr, threads=NT), label="staged once")
+    with pytest.raises(svdag.SvdError) as e:
+        svdag.svd_view_trace(w, f1, outs[0])
+    assert e.value.code == svdag.SVD_EINVAL
+
+
 def test_upload_replace_evict(env):
     svdag, torch = env
     rng = np.random.default_rng(77)
