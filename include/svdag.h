@@ -175,9 +175,31 @@ int svd_world_pool_used(const svd_world* w, size_t* used);
  * has no room (nothing is changed then); SVD_EINVAL if the blob's chunk size
  * or LOD count differ from the world's. */
 int svd_chunk_upload(svd_world* w, const uint32_t c[3], const svd_blob* b, void* stream);
-/* Release chunk c's pool space.  Work already enqueued on the world's stream
- * still sees the old data (stream order). */
+/* Release chunk c's pool space; the chunk counts as never uploaded again.
+ * Work already enqueued on the world's stream still sees the old data
+ * (stream order). */
 int svd_chunk_evict(svd_world* w, const uint32_t c[3]);
+
+/* Per-LOD residency, for streaming (Section 3.4: LODs are loaded and
+ * unloaded by camera distance).  A (chunk, LOD) slot is never uploaded,
+ * described (its tight box and solid count are known, its DAG is not in the
+ * pool) or resident.
+ * svd_chunk_upload_lods: makes the LODs in lod_mask (bit k = LOD k) resident
+ *   from b and describes every LOD of the chunk from b; LODs outside the mask
+ *   that are resident stay so (they must hold the same chunk content).  All
+ *   or nothing: SVD_ENOMEM leaves the world unchanged.  lod_mask 0 only
+ *   describes the chunk.  H2D copies and descriptor writes on `stream`.
+ * svd_chunk_evict_lods: the LODs in lod_mask go back to described and their
+ *   pool space is released; descriptor writes on `stream`.  The caller
+ *   orders later uploads that may reuse the space after every trace that
+ *   still reads it.
+ * A view traced while a LOD it needs (picked, not culled, not empty) is only
+ * described writes, for every ray that reaches that chunk, a record with
+ * hit = 0, t = +inf and chunk = SVD_CHUNK_NOT_LOADED instead of reading it. */
+#define SVD_CHUNK_NOT_LOADED 0xFFFFFFFDu
+int svd_chunk_upload_lods(svd_world* w, const uint32_t c[3], const svd_blob* b, uint32_t lod_mask,
+                          void* stream);
+int svd_chunk_evict_lods(svd_world* w, const uint32_t c[3], uint32_t lod_mask, void* stream);
 
 /* Exact integer frame of a camera (host, FP64 with fixed operation order).
  * SVD_EINVAL for a degenerate camera, SVD_ERANGE if the position is outside
@@ -188,8 +210,8 @@ int svd_camera_frame(const svd_camera* cam, svd_ray_frame* out);
  * chunk) and the per-pixel trace on `stream`.
  *   out_dev  width*height svd_hit records (device, caller-owned).
  *   flags    SVD_NO_CULL or 0.
- * Errors: SVD_EINVAL, SVD_ERANGE (camera), SVD_ENOTFOUND (a chunk was never
- * uploaded), SVD_EDEVICE. */
+ * Errors: SVD_EINVAL, SVD_ERANGE (camera), SVD_ENOTFOUND (some (chunk, LOD)
+ * was never uploaded nor described), SVD_EDEVICE. */
 int svd_trace_view(svd_world* w, const svd_camera* cam, svd_hit* out_dev, uint32_t flags,
                    void* stream);
 /* Same, from an integer frame (directions must satisfy |D| < 2^31 over the
@@ -266,6 +288,78 @@ int svd_batch_get_tiling(const svd_batch* b, uint32_t* tile_w, uint32_t* claim, 
  * (may be NULL). */
 int svd_batch_tune(svd_batch* b, const svd_camera* cams, uint32_t n, svd_hit* out_dev,
                    uint64_t out_records, uint32_t reps, void* stream, float* best_ms);
+
+/* ------------------------------------------------------------------------
+ * Serving: view requests of any resolution, arriving at any time, over a
+ * world whose pool may hold only part of the map (Section 3.4 streaming:
+ * chunk LODs are loaded by camera distance and unloaded when space is
+ * needed).  A worker thread owns the world while the server lives (the
+ * caller makes no other call on it meanwhile):
+ *   - requests are admitted in arrival order; the (chunk, LOD) slots a view
+ *     reads (the chunk stage's LOD pick and cull, evaluated on the host) are
+ *     pinned, missing ones uploaded from the chunk's source blob on an
+ *     upload stream, evicting unpinned slots least recently used first; a
+ *     request waits while in-flight work holds the memory it needs and
+ *     fails with SVD_ENOMEM if it does not fit the idle pool;
+ *   - SVD_SERVE_BATCHED packs admitted requests (same flags, up to max_views
+ *     views and max_rays rays) into captured batch launches, up to
+ *     `inflight` of them on the device at once, each on its own stream;
+ *     requests arriving meanwhile join the next launch as soon as a launch
+ *     slot frees (continuous batching);
+ *   - SVD_SERVE_PLAIN traces each request with its own stage + trace launch
+ *     pair, all on one stream, up to `inflight` queued (the per-request
+ *     comparison).
+ * Each request's records equal those of svd_trace_view of the same camera
+ * on a world with every chunk resident.
+ * ------------------------------------------------------------------------ */
+typedef struct svd_server svd_server;
+
+#define SVD_SERVE_BATCHED 0u
+#define SVD_SERVE_PLAIN 1u
+
+typedef struct {
+  uint32_t mode;           /* SVD_SERVE_BATCHED or SVD_SERVE_PLAIN */
+  uint32_t max_views;      /* batched: requests per launch, 1..1024 */
+  uint32_t inflight;       /* launches on the device at once, 1..8 */
+  uint32_t tile_w, claim;  /* batched: tiling (0 = the batch default) */
+  uint32_t blocks_per_cu;  /* batched: persistent grid (0 = the batch default) */
+  uint64_t max_rays;       /* batched: rays per launch (a larger request goes alone) */
+} svd_server_desc;
+
+typedef struct {
+  uint64_t tag;            /* the caller's tag of the request */
+  int32_t status;          /* SVD_OK, or the error that failed the request */
+  uint32_t batch_views;    /* requests in the launch that traced it (0 if none) */
+  double t_submit, t_launch, t_done;  /* seconds on the server's clock: submit call,
+                                         launch enqueued, completion seen by the worker */
+} svd_request_done;
+
+typedef struct {
+  uint64_t submitted, completed, failed, launches;
+  uint64_t uploads, upload_bytes, evictions, evict_bytes;
+  uint64_t memory_waits;   /* requests that waited for in-flight work to release memory */
+  uint64_t pool_used;      /* pool bytes holding chunk LODs */
+} svd_server_stats;
+
+/* Batched mode takes inflight x svd_batch_create(w, max_views) pool space.
+ * Errors: SVD_EINVAL, SVD_ENOMEM, SVD_EDEVICE. */
+int svd_server_create(svd_world* w, const svd_server_desc* d, svd_server** out);
+/* Source of chunk c's LODs (kept alive by the caller until the server is
+ * destroyed); describes the chunk in the world.  Every chunk needs one
+ * before the first submit; none may change after it (SVD_EINVAL). */
+int svd_server_set_chunk(svd_server* s, const uint32_t c[3], const svd_blob* b);
+/* Queue a request; returns at once.  out_dev: width*height records (device),
+ * with no pending work of the caller's (the server's streams do not wait
+ * for other streams) and untouched until the request is reported done.  flags:
+ * SVD_NO_CULL or 0.  Camera errors as svd_camera_frame, synchronously.
+ * Thread-safe. */
+int svd_server_submit(svd_server* s, const svd_camera* cam, svd_hit* out_dev, uint32_t flags, uint64_t tag);
+/* Up to `max` finished requests (oldest first) into out, their count in *n;
+ * waits up to wait_us microseconds for the first.  Thread-safe. */
+int svd_server_poll(svd_server* s, svd_request_done* out, uint32_t max, uint32_t* n, uint32_t wait_us);
+int svd_server_stats_get(svd_server* s, svd_server_stats* st);
+/* Completes every submitted request, then frees the server (not the world). */
+void svd_server_destroy(svd_server* s);
 
 #ifdef __cplusplus
 }

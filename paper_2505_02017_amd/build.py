@@ -13,11 +13,11 @@ LIB = os.path.join(HERE, "libsvdag.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall",
+COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall", "-pthread",
           f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 # Packed FP32 instructions stay off (toolchain notes).
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["builder.cpp", "runtime.cpp", "kernels.hip"]
+SOURCES = ["builder.cpp", "runtime.cpp", "server.cpp", "kernels.hip"]
 
 
 def _run(cmd, verbose):
@@ -41,7 +41,7 @@ def build_lib(verbose: bool = False) -> str:
         _run([HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([HIPCC, *DEVICE, "-shared", "-fPIC", "-o", tmp, *objs], verbose)
+    _run([HIPCC, *DEVICE, "-shared", "-fPIC", "-pthread", "-o", tmp, *objs], verbose)
     os.replace(tmp, LIB)
     return LIB
 

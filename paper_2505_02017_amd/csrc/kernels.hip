@@ -88,8 +88,12 @@ __host__ __device__ inline uint32_t stage_chunk(const StageParams& p, uint32_t c
     }
     if (culled) v |= kViewCulled;
   }
+  // a chunk that rays may enter at an LOD that is described but not loaded
+  if (!(v & (kViewCulled | kViewEmpty)) && d.nodes == 0) v |= kViewMissing;
   return v;
 }
+
+uint32_t host_stage_chunk(const StageParams& p, uint32_t ci) { return stage_chunk(p, ci); }
 
 __global__ void chunk_stage_kernel(StageParams p) {
   const uint32_t ci = blockIdx.x * blockDim.x + threadIdx.x;
@@ -111,8 +115,9 @@ constexpr int kBlock = 256;      // 4 waves; each wave is one 8x8 pixel tile
 constexpr int kStackLevels = 8;  // node levels 3..10
 constexpr uint32_t kMaxIter = 1u << 22;
 constexpr uint32_t kFaultChunk = 0xFFFFFFFEu;
+constexpr uint32_t kMissingChunk = 0xFFFFFFFDu;
 
-enum : uint32_t { kRunning = 0, kHit = 1, kMiss = 2, kFault = 3 };
+enum : uint32_t { kRunning = 0, kHit = 1, kMiss = 2, kFault = 3, kNotLoaded = 4 };
 
 __host__ __device__ __forceinline__ uint32_t float_bits(float f) {
   union { float f; uint32_t u; } v;
@@ -223,6 +228,9 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
       const uint32_t v = p.view[ci];
       if (v & (kViewCulled | kViewEmpty)) {
         step = true;
+      } else if (v & kViewMissing) {
+        status = kNotLoaded;
+        break;
       } else {
         k = (int)(v & kViewLodMask);
         const DevDag* dag = &p.desc[(size_t)ci * 4 + k];
@@ -313,6 +321,7 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
 
   uint4 rec = make_uint4(0u, 0u, 0x7F800000u /* +inf */, 0xFFFFFFFFu);
   if (status == kFault) rec.w = kFaultChunk;
+  if (status == kNotLoaded) rec.w = kMissingChunk;
   if (status == kHit) {
     // unmirrored LOD-k cell
     int32_t h[3];
@@ -436,7 +445,6 @@ __global__ __launch_bounds__(kBlock) void batch_trace_kernel(BatchParams p) {
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t total = p.hdr->total_tiles, nviews = p.hdr->nviews;
   const uint32_t claim = p.hdr->claim, tw = p.hdr->tile_w, th = 64 / tw;
-  svd_hit* out = (svd_hit*)p.hdr->out;
   for (;;) {
     // one queue access per wave: lane 0 claims, the wave shares the index
     uint32_t t0 = 0;
@@ -466,8 +474,7 @@ __global__ __launch_bounds__(kBlock) void batch_trace_kernel(BatchParams p) {
       tp.chunk_log2 = p.chunk_log2;
       tp.view = p.view_tables + (size_t)lo * p.nchunks;
       tp.desc = p.desc;
-      reinterpret_cast<uint4*>(out)[bv.out_offset + (size_t)py * bv.W + px] =
-          trace_pixel(tp, px, py, &stk[0][tid], kBlock);
+      reinterpret_cast<uint4*>(bv.out)[(size_t)py * bv.W + px] = trace_pixel(tp, px, py, &stk[0][tid], kBlock);
     }
   }
 }

@@ -119,65 +119,6 @@ extern "C" int svd_camera_frame(const svd_camera* cam, svd_ray_frame* out) {
 }
 
 // ------------------------------------------------------------------ world
-// Default persistent grid of the per-view trace.  Fewer resident waves than
-// fit a CU trace 1440p views faster (blocks per CU 6 / 5 / 4 / 3: 3.87 /
-// 4.07 / 4.21 / 4.16 Grays/s on the 16x16-chunk map; contention of more
-// resident rays for the CU's cache is the likely cause).
-constexpr uint32_t kViewBlocksPerCu = 4;
-
-struct svd_world {
-  svd_world_desc desc;
-  uint32_t nchunks = 0;
-  uint8_t* pool = nullptr;
-  size_t pool_bytes = 0;
-  DevDag* d_desc = nullptr;
-  uint32_t* d_view = nullptr;
-  uint32_t* d_queue = nullptr;  // per-view trace work queue (256-byte control block)
-  uint32_t cus = 0;             // compute units of the device
-  uint32_t max_per_cu = 0;      // resident trace blocks per CU at full occupancy
-  uint32_t per_cu = 0;          // trace blocks per CU in use (persistent grid = per_cu x cus)
-  size_t data_begin = 0;
-  std::map<size_t, size_t> free_blocks;  // offset -> bytes
-  struct Region { size_t off = 0, bytes = 0; bool resident = false; };
-  std::vector<Region> region;
-  uint32_t missing = 0;  // chunks never uploaded or evicted
-  size_t used = 0;
-  svd_ray_frame staged;  // frame of the last chunk stage (its view table)
-  bool has_staged = false;
-
-  bool alloc(size_t bytes, size_t* off) {
-    bytes = (bytes + 255) / 256 * 256;
-    for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
-      if (it->second < bytes) continue;
-      *off = it->first;
-      const size_t rest = it->second - bytes;
-      const size_t roff = it->first + bytes;
-      free_blocks.erase(it);
-      if (rest) free_blocks[roff] = rest;
-      used += bytes;
-      return true;
-    }
-    return false;
-  }
-  void release(size_t off, size_t bytes) {
-    bytes = (bytes + 255) / 256 * 256;
-    used -= bytes;
-    auto it = free_blocks.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_blocks.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_blocks.erase(nx);
-    }
-    if (it != free_blocks.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_blocks.erase(it);
-      }
-    }
-  }
-};
-
 static int check_desc(const svd_world_desc* d) {
   if (d->chunk_log2 < 3 || d->chunk_log2 > 10) return svd_fail(SVD_EINVAL, "world: chunk_log2 must be 3..10");
   if (d->lod_count < 1 || d->lod_count > 4 || (int)d->chunk_log2 - (int)(d->lod_count - 1) < 3)
@@ -221,8 +162,10 @@ extern "C" int svd_world_create(const svd_world_desc* desc, void* pool_dev, size
     w->per_cu = std::min(per_cu, kViewBlocksPerCu);
     w->data_begin = desc_bytes + view_bytes + ctl_bytes;
     if (pool_bytes > w->data_begin) w->free_blocks[w->data_begin] = (pool_bytes - w->data_begin) / 256 * 256;
-    w->region.resize(n);
-    w->missing = (uint32_t)n;
+    w->slot.resize((size_t)n * 4);
+    w->h_desc.assign((size_t)n * 4, DevDag());
+    memset(w->h_desc.data(), 0, w->h_desc.size() * sizeof(DevDag));
+    w->absent = (uint32_t)n * desc->lod_count;
     hipError_t e = hipMemset(pool_dev, 0, w->data_begin);
     if (e != hipSuccess) {
       delete w;
@@ -251,59 +194,135 @@ static int chunk_index(const svd_world* w, const uint32_t c[3], uint32_t* ci) {
   return SVD_OK;
 }
 
-extern "C" int svd_chunk_upload(svd_world* w, const uint32_t c[3], const svd_blob* b, void* stream) {
-  if (!w || !b) return svd_fail(SVD_EINVAL, "svd_chunk_upload: null argument");
+// Descriptor of LOD k of blob b whose device image section starts at pool
+// offset `off` (addresses zero when the LOD is only described).
+static DevDag lod_desc(const svd_world* w, const svd_blob* b, uint32_t k, bool loaded, size_t off) {
+  DevDag d;
+  memset(&d, 0, sizeof(d));
+  const LodData& L = b->lod[k];
+  if (loaded) {
+    const uint64_t base = (uint64_t)(uintptr_t)(w->pool + off) - L.off_begin;
+    d.nodes = base + L.off_nodes;
+    d.leaves = base + L.off_leaves;
+    d.pre = base + L.off_pre;
+    d.rle_start = base + L.off_rle_start;
+    d.rle_mat = base + L.off_rle_mat;
+  }
+  d.rle_n = (uint32_t)L.rle_start.size();
+  d.root = L.root_word;
+  d.solid = L.n_solid;
+  for (int a = 0; a < 3; a++) {
+    d.lo[a] = L.lo[a];
+    d.hi[a] = L.hi[a];
+  }
+  return d;
+}
+
+int world_upload_lods(svd_world* w, uint32_t ci, const svd_blob* b, uint32_t mask, hipStream_t s) {
+  if (b->chunk_log2 != w->desc.chunk_log2 || b->lod_count != w->desc.lod_count)
+    return svd_fail(SVD_EINVAL, "upload: blob chunk size or LOD count differs from the world's");
+  const uint32_t nl = w->desc.lod_count;
+  if (mask >> nl) return svd_fail(SVD_EINVAL, "upload: LOD mask 0x%x beyond %u LODs", mask, nl);
+  size_t off[4] = {0, 0, 0, 0}, bytes[4] = {0, 0, 0, 0};
+  for (uint32_t k = 0; k < nl; k++) {
+    if (!((mask >> k) & 1)) continue;
+    bytes[k] = b->lod[k].off_end - b->lod[k].off_begin;
+    if (bytes[k] && !w->alloc(bytes[k], &off[k])) {
+      for (uint32_t j = 0; j < k; j++)
+        if (bytes[j]) w->release(off[j], bytes[j]);
+      return svd_fail(SVD_ENOMEM, "upload: pool full (%zu bytes requested, %zu used of %zu)", bytes[k], w->used,
+                      w->pool_bytes - w->data_begin);
+    }
+  }
+  hipError_t e = hipSuccess;
+  for (uint32_t k = 0; k < nl && e == hipSuccess; k++)
+    if (bytes[k])
+      e = hipMemcpyAsync(w->pool + off[k], b->image.data() + b->lod[k].off_begin, bytes[k], hipMemcpyHostToDevice, s);
+  DevDag d[4];
+  memset(d, 0, sizeof(d));
+  const size_t base = (size_t)ci * 4;
+  for (uint32_t k = 0; k < nl; k++) {
+    const bool load = (mask >> k) & 1;
+    d[k] = lod_desc(w, b, k, load, off[k]);
+    if (!load && w->slot[base + k].state == svd_world::kResident) {  // keep what is loaded
+      d[k].nodes = w->h_desc[base + k].nodes;
+      d[k].leaves = w->h_desc[base + k].leaves;
+      d[k].pre = w->h_desc[base + k].pre;
+      d[k].rle_start = w->h_desc[base + k].rle_start;
+      d[k].rle_mat = w->h_desc[base + k].rle_mat;
+    }
+  }
+  int rc = e == hipSuccess ? launch_set_desc(w->d_desc + base, d, 4, s)
+                           : svd_fail(SVD_EDEVICE, "upload: hipMemcpyAsync: %s", hipGetErrorString(e));
+  if (rc) {
+    for (uint32_t k = 0; k < nl; k++)
+      if (bytes[k]) w->release(off[k], bytes[k]);
+    return rc;
+  }
+  for (uint32_t k = 0; k < nl; k++) {
+    svd_world::Slot& sl = w->slot[base + k];
+    if (sl.state == svd_world::kAbsent) w->absent--;
+    if ((mask >> k) & 1) {
+      if (sl.state == svd_world::kResident && sl.bytes) w->release(sl.off, sl.bytes);
+      sl.off = off[k];
+      sl.bytes = bytes[k];
+      sl.state = svd_world::kResident;
+    } else if (sl.state == svd_world::kAbsent) {
+      sl.state = svd_world::kDescribed;
+    }
+    w->h_desc[base + k] = d[k];
+  }
+  return SVD_OK;
+}
+
+int world_evict_lods(svd_world* w, uint32_t ci, uint32_t mask, hipStream_t s) {
+  const uint32_t nl = w->desc.lod_count;
+  if (mask >> nl) return svd_fail(SVD_EINVAL, "evict: LOD mask 0x%x beyond %u LODs", mask, nl);
+  const size_t base = (size_t)ci * 4;
+  DevDag d[4];
+  bool change = false;
+  for (uint32_t k = 0; k < 4; k++) {
+    d[k] = w->h_desc[base + k];
+    if (k < nl && ((mask >> k) & 1) && w->slot[base + k].state == svd_world::kResident) {
+      d[k].nodes = d[k].leaves = d[k].pre = d[k].rle_start = d[k].rle_mat = 0;
+      change = true;
+    }
+  }
+  if (!change) return SVD_OK;
+  int rc = launch_set_desc(w->d_desc + base, d, 4, s);
+  if (rc) return rc;
+  for (uint32_t k = 0; k < nl; k++) {
+    svd_world::Slot& sl = w->slot[base + k];
+    if (((mask >> k) & 1) && sl.state == svd_world::kResident) {
+      if (sl.bytes) w->release(sl.off, sl.bytes);
+      sl.off = sl.bytes = 0;
+      sl.state = svd_world::kDescribed;
+    }
+    w->h_desc[base + k] = d[k];
+  }
+  return SVD_OK;
+}
+
+extern "C" int svd_chunk_upload_lods(svd_world* w, const uint32_t c[3], const svd_blob* b, uint32_t lod_mask,
+                                     void* stream) {
+  if (!w || !b) return svd_fail(SVD_EINVAL, "svd_chunk_upload_lods: null argument");
   uint32_t ci;
   int rc = chunk_index(w, c, &ci);
   if (rc) return rc;
-  if (b->chunk_log2 != w->desc.chunk_log2 || b->lod_count != w->desc.lod_count)
-    return svd_fail(SVD_EINVAL, "upload: blob chunk size or LOD count differs from the world's");
-  size_t off = 0;
-  const size_t bytes = b->image.size();
-  if (bytes && !w->alloc(bytes, &off))
-    return svd_fail(SVD_ENOMEM, "upload: pool full (%zu bytes requested, %zu used of %zu)", bytes, w->used,
-                    w->pool_bytes - w->data_begin);
-  hipStream_t s = (hipStream_t)stream;
-  if (bytes) {
-    hipError_t e = hipMemcpyAsync(w->pool + off, b->image.data(), bytes, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) {
-      w->release(off, bytes);
-      return svd_fail(SVD_EDEVICE, "upload: hipMemcpyAsync: %s", hipGetErrorString(e));
-    }
-  }
-  DevDag d[4];
-  memset(d, 0, sizeof(d));
-  const uint64_t base = (uint64_t)(uintptr_t)(w->pool + off);
-  for (uint32_t k = 0; k < b->lod_count; k++) {
-    const LodData& L = b->lod[k];
-    d[k].nodes = base + L.off_nodes;
-    d[k].leaves = base + L.off_leaves;
-    d[k].pre = base + L.off_pre;
-    d[k].rle_start = base + L.off_rle_start;
-    d[k].rle_mat = base + L.off_rle_mat;
-    d[k].rle_n = (uint32_t)L.rle_start.size();
-    d[k].root = L.root_word;
-    d[k].solid = L.n_solid;
-    for (int a = 0; a < 3; a++) {
-      d[k].lo[a] = L.lo[a];
-      d[k].hi[a] = L.hi[a];
-    }
-  }
-  rc = launch_set_desc(w->d_desc + (size_t)ci * 4, d, 4, stream);
-  if (rc) {
-    if (bytes) w->release(off, bytes);
-    return rc;
-  }
-  svd_world::Region& r = w->region[ci];
-  if (r.resident) {
-    if (r.bytes) w->release(r.off, r.bytes);
-  } else {
-    w->missing--;
-  }
-  r.off = off;
-  r.bytes = bytes;
-  r.resident = true;
-  return SVD_OK;
+  return world_upload_lods(w, ci, b, lod_mask, (hipStream_t)stream);
+}
+
+extern "C" int svd_chunk_upload(svd_world* w, const uint32_t c[3], const svd_blob* b, void* stream) {
+  if (!w || !b) return svd_fail(SVD_EINVAL, "svd_chunk_upload: null argument");
+  return svd_chunk_upload_lods(w, c, b, (1u << w->desc.lod_count) - 1, stream);
+}
+
+extern "C" int svd_chunk_evict_lods(svd_world* w, const uint32_t c[3], uint32_t lod_mask, void* stream) {
+  if (!w) return svd_fail(SVD_EINVAL, "svd_chunk_evict_lods: null world");
+  uint32_t ci;
+  int rc = chunk_index(w, c, &ci);
+  if (rc) return rc;
+  return world_evict_lods(w, ci, lod_mask, (hipStream_t)stream);
 }
 
 extern "C" int svd_chunk_evict(svd_world* w, const uint32_t c[3]) {
@@ -311,11 +330,16 @@ extern "C" int svd_chunk_evict(svd_world* w, const uint32_t c[3]) {
   uint32_t ci;
   int rc = chunk_index(w, c, &ci);
   if (rc) return rc;
-  svd_world::Region& r = w->region[ci];
-  if (!r.resident) return svd_fail(SVD_ENOTFOUND, "evict: chunk not resident");
-  if (r.bytes) w->release(r.off, r.bytes);
-  r = svd_world::Region();
-  w->missing++;
+  bool any = false;
+  for (uint32_t k = 0; k < w->desc.lod_count; k++) {
+    svd_world::Slot& sl = w->slot[(size_t)ci * 4 + k];
+    if (sl.state == svd_world::kAbsent) continue;
+    any = true;
+    if (sl.state == svd_world::kResident && sl.bytes) w->release(sl.off, sl.bytes);
+    sl = svd_world::Slot();
+    w->absent++;
+  }
+  if (!any) return svd_fail(SVD_ENOTFOUND, "evict: chunk not resident");
   return SVD_OK;
 }
 
@@ -372,22 +396,27 @@ static bool same_frame(const svd_ray_frame& a, const svd_ray_frame& b) {
          a.width == b.width && a.height == b.height;
 }
 
-extern "C" int svd_view_stage(svd_world* w, const svd_ray_frame* f, uint32_t flags, void* stream) {
-  if (!w || !f) return svd_fail(SVD_EINVAL, "svd_view_stage: null argument");
-  if (flags & ~SVD_NO_CULL) return svd_fail(SVD_EINVAL, "stage: unknown flags");
-  int rc = check_frame(f);
-  if (rc) return rc;
-  if (w->missing) return svd_fail(SVD_ENOTFOUND, "stage: %u chunks are not resident", w->missing);
+StageParams world_stage_params(const svd_world* w, const svd_ray_frame* f, bool no_cull, const DevDag* desc) {
   StageParams sp;
   memset(&sp, 0, sizeof(sp));
   memcpy(sp.O, f->O, sizeof(sp.O));
-  sp.cull = !(flags & SVD_NO_CULL) && cull_planes(f, sp.n);
+  sp.cull = !no_cull && cull_planes(f, sp.n);
   memcpy(sp.grid, w->desc.grid, sizeof(sp.grid));
   sp.chunk_log2 = w->desc.chunk_log2;
   sp.lod_count = w->desc.lod_count;
   memcpy(sp.thr, w->desc.lod_threshold, sizeof(sp.thr));
   sp.nchunks = w->nchunks;
-  sp.desc = w->d_desc;
+  sp.desc = desc;
+  return sp;
+}
+
+extern "C" int svd_view_stage(svd_world* w, const svd_ray_frame* f, uint32_t flags, void* stream) {
+  if (!w || !f) return svd_fail(SVD_EINVAL, "svd_view_stage: null argument");
+  if (flags & ~SVD_NO_CULL) return svd_fail(SVD_EINVAL, "stage: unknown flags");
+  int rc = check_frame(f);
+  if (rc) return rc;
+  if (w->absent) return svd_fail(SVD_ENOTFOUND, "stage: %u (chunk, LOD) slots were never uploaded", w->absent);
+  StageParams sp = world_stage_params(w, f, flags & SVD_NO_CULL, w->d_desc);
   sp.view = w->d_view;
   rc = launch_chunk_stage(sp, stream);
   if (rc) return rc;
@@ -400,7 +429,7 @@ extern "C" int svd_view_trace(svd_world* w, const svd_ray_frame* f, svd_hit* out
   if (!w || !f || !out_dev) return svd_fail(SVD_EINVAL, "svd_view_trace: null argument");
   if (!w->has_staged || !same_frame(w->staged, *f))
     return svd_fail(SVD_EINVAL, "trace: the frame was not staged by the last svd_view_stage");
-  if (w->missing) return svd_fail(SVD_ENOTFOUND, "trace: %u chunks are not resident", w->missing);
+  if (w->absent) return svd_fail(SVD_ENOTFOUND, "trace: %u (chunk, LOD) slots were never uploaded", w->absent);
   const uint32_t W = f->width, H = f->height;
   TraceParams tp;
   memset(&tp, 0, sizeof(tp));
@@ -465,28 +494,6 @@ extern "C" int svd_view_table(svd_world* w, uint32_t* out, uint32_t n, void* str
 }
 
 // ------------------------------------------------------------ view batches
-// Device memory of a batch comes from the world's pool:
-//   [BatchHeader 64 B | pad to 256][BatchView x max_views][view tables: max_views x nchunks u32]
-// Host staging (header + views) is pinned; an event guards its reuse.
-struct svd_batch {
-  svd_world* w = nullptr;
-  uint32_t max_views = 0;
-  size_t off = 0, bytes = 0;
-  BatchHeader* d_hdr = nullptr;
-  BatchView* d_views = nullptr;
-  uint32_t* d_tables = nullptr;
-  uint8_t* h_stage = nullptr;      // pinned: header + views
-  size_t stage_bytes = 0;
-  hipEvent_t staged = nullptr;     // the last upload of h_stage has been consumed
-  hipEvent_t finished = nullptr;   // the last graph launch has completed
-  bool stage_pending = false;
-  bool launched = false;
-  hipStream_t cap = nullptr;       // capture stream (default priority)
-  hipGraphExec_t exec = nullptr;
-  uint32_t cus = 0, max_per_cu = 0, per_cu = 0;  // persistent grid = per_cu x cus blocks
-  uint32_t tile_w = 8, claim = 1;
-};
-
 // Capture reset + stage + persistent trace as the batch's graph (again after
 // an occupancy change); every batch reuses it.
 static int batch_capture(svd_batch* b) {
@@ -613,23 +620,20 @@ extern "C" int svd_batch_get_tiling(const svd_batch* b, uint32_t* tile_w, uint32
   return SVD_OK;
 }
 
-extern "C" int svd_batch_trace_frames(svd_batch* b, const svd_ray_frame* frames, uint32_t n,
-                                      svd_hit* out_dev, uint64_t out_records, uint32_t flags, void* stream) {
-  if (!b || !frames || !out_dev || n == 0) return svd_fail(SVD_EINVAL, "svd_batch_trace: bad argument");
-  if (n > b->max_views) return svd_fail(SVD_EINVAL, "batch: %u views > max %u", n, b->max_views);
+int batch_enqueue(svd_batch* b, const svd_ray_frame* frames, svd_hit* const* outs, uint32_t n, uint32_t flags,
+                  hipStream_t s) {
+  if (n == 0 || n > b->max_views) return svd_fail(SVD_EINVAL, "batch: %u views, 1..%u allowed", n, b->max_views);
   if (flags & ~SVD_NO_CULL) return svd_fail(SVD_EINVAL, "batch: unknown flags");
   svd_world* w = b->w;
-  if (w->missing) return svd_fail(SVD_ENOTFOUND, "batch: %u chunks are not resident", w->missing);
+  if (w->absent) return svd_fail(SVD_ENOTFOUND, "batch: %u (chunk, LOD) slots were never uploaded", w->absent);
   const uint32_t tw = b->tile_w, th = 64 / tw;
-  uint64_t px_total = 0, tiles = 0;
+  uint64_t tiles = 0;
   for (uint32_t v = 0; v < n; v++) {
     int rc = check_frame(&frames[v]);
     if (rc) return rc;
-    px_total += (uint64_t)frames[v].width * frames[v].height;
+    if (!outs[v]) return svd_fail(SVD_EINVAL, "batch: null output for view %u", v);
     tiles += (uint64_t)((frames[v].width + tw - 1) / tw) * ((frames[v].height + th - 1) / th);
   }
-  if (px_total > out_records) return svd_fail(SVD_EINVAL, "batch: output holds %llu records, views need %llu",
-                                              (unsigned long long)out_records, (unsigned long long)px_total);
   if (tiles >= (1ull << 31)) return svd_fail(SVD_EINVAL, "batch: too many tiles");
   // the previous upload must have left the staging buffer before it is rewritten
   if (b->stage_pending) {
@@ -640,12 +644,10 @@ extern "C" int svd_batch_trace_frames(svd_batch* b, const svd_ray_frame* frames,
   BatchHeader* h = (BatchHeader*)b->h_stage;
   BatchView* vs = (BatchView*)(b->h_stage + 256);
   memset(h, 0, sizeof(*h));
-  h->out = (uint64_t)(uintptr_t)out_dev;
   h->nviews = n;
   h->total_tiles = (uint32_t)tiles;
   h->tile_w = tw;
   h->claim = b->claim;
-  uint64_t off = 0;
   uint32_t tbase = 0;
   for (uint32_t v = 0; v < n; v++) {
     const svd_ray_frame& f = frames[v];
@@ -656,15 +658,13 @@ extern "C" int svd_batch_trace_frames(svd_batch* b, const svd_ray_frame* frames,
     memcpy(bv.BX, f.BX, sizeof(bv.BX));
     memcpy(bv.BY, f.BY, sizeof(bv.BY));
     bv.cull = !(flags & SVD_NO_CULL) && cull_planes(&f, bv.n);
-    bv.out_offset = off;
+    bv.out = (uint64_t)(uintptr_t)outs[v];
     bv.W = f.width;
     bv.H = f.height;
     bv.tiles_x = (f.width + tw - 1) / tw;
     bv.tile_base = tbase;
-    off += (uint64_t)f.width * f.height;
     tbase += bv.tiles_x * ((f.height + th - 1) / th);
   }
-  hipStream_t s = (hipStream_t)stream;
   HIP_OK(hipMemcpyAsync(b->d_hdr, b->h_stage, 256 + (size_t)n * sizeof(BatchView), hipMemcpyHostToDevice, s));
   HIP_OK(hipEventRecord(b->staged, s));
   b->stage_pending = true;
@@ -672,6 +672,21 @@ extern "C" int svd_batch_trace_frames(svd_batch* b, const svd_ray_frame* frames,
   HIP_OK(hipEventRecord(b->finished, s));
   b->launched = true;
   return SVD_OK;
+}
+
+extern "C" int svd_batch_trace_frames(svd_batch* b, const svd_ray_frame* frames, uint32_t n,
+                                      svd_hit* out_dev, uint64_t out_records, uint32_t flags, void* stream) {
+  if (!b || !frames || !out_dev || n == 0) return svd_fail(SVD_EINVAL, "svd_batch_trace: bad argument");
+  if (n > b->max_views) return svd_fail(SVD_EINVAL, "batch: %u views > max %u", n, b->max_views);
+  std::vector<svd_hit*> outs(n);
+  uint64_t px_total = 0;
+  for (uint32_t v = 0; v < n; v++) {
+    outs[v] = out_dev + px_total;
+    px_total += (uint64_t)frames[v].width * frames[v].height;
+  }
+  if (px_total > out_records) return svd_fail(SVD_EINVAL, "batch: output holds %llu records, views need %llu",
+                                              (unsigned long long)out_records, (unsigned long long)px_total);
+  return batch_enqueue(b, frames, outs.data(), n, flags, (hipStream_t)stream);
 }
 
 extern "C" int svd_batch_trace(svd_batch* b, const svd_camera* cams, uint32_t n, svd_hit* out_dev,

@@ -1,0 +1,453 @@
+// Request server of libsvdag: view requests of any size, arriving at any
+// time, over a world whose pool holds only part of the map.
+//
+// One worker thread owns the world while the server lives.  It
+//   - admits pending requests in arrival order: the chunk stage's decision
+//     is evaluated on the host (the same function the GPU stage runs) to get
+//     the (chunk, LOD) slots the view reads; resident ones are pinned,
+//     missing ones are uploaded on the upload stream, evicting unpinned
+//     slots in least-recently-used order when the pool is full.  A request
+//     that does not fit while other work holds memory waits; one that does
+//     not fit an idle pool fails with SVD_ENOMEM;
+//   - packs admitted requests into launches (batched mode: up to max_views
+//     requests and max_rays rays per captured batch graph; plain mode: one
+//     stage + trace launch pair per request) and keeps up to `inflight`
+//     launches on the device, so requests that arrive while others run are
+//     admitted as soon as a launch slot and memory free up (continuous
+//     batching);
+//   - reaps finished launches (event query), unpins their slots and reports
+//     each request's submit, launch and completion times.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "svdag_internal.h"
+
+using namespace svd;
+
+namespace {
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+  uint64_t tag = 0;
+  svd_ray_frame frame;
+  svd_hit* out = nullptr;
+  uint32_t flags = 0;
+  double t_submit = 0;
+  std::vector<uint32_t> need;  // slots (chunk * 4 + lod) the view reads
+  bool staged = false;         // `need` is computed
+  bool waited = false;         // has waited for memory
+};
+
+struct Flight {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  svd_batch* batch = nullptr;  // batched mode
+  std::vector<Request> reqs;
+  double t_launch = 0;
+  bool busy = false;
+};
+
+enum { kAdmitted = 0, kWait = 1 };  // admit(): or a negative SVD error
+}  // namespace
+
+struct svd_server {
+  svd_world* w = nullptr;
+  svd_server_desc d;
+  int device = 0;
+  Clock::time_point t0;
+  std::vector<const svd_blob*> src;  // per chunk: where its LODs are uploaded from
+  uint32_t sources = 0;
+  std::vector<uint32_t> pins;        // per slot: in-flight or admitted requests reading it
+  std::vector<uint64_t> last_use;    // per slot: admission sequence of its last reader
+  uint64_t use_seq = 0;
+  uint64_t data_bytes = 0;           // pool bytes of resident chunk LODs
+  hipStream_t up = nullptr;          // uploads and descriptor writes
+  hipEvent_t up_done = nullptr;      // after the latest admission's uploads
+  bool up_pending = false;
+  hipStream_t plain = nullptr;       // plain mode: every launch (the world has one view table)
+  std::vector<Flight> fl;
+
+  std::mutex mu;                     // guards everything below
+  std::condition_variable wake;      // worker: submissions, stop
+  std::condition_variable done_cv;   // pollers
+  std::deque<Request> inbox;
+  std::deque<svd_request_done> done;
+  svd_server_stats st;
+  bool started = false, stop = false;
+  std::thread th;
+
+  std::deque<Request> pending;       // worker-owned
+
+  double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+};
+
+static bool any_busy(const svd_server* s) {
+  for (const Flight& f : s->fl)
+    if (f.busy) return true;
+  return false;
+}
+
+static void finish(svd_server* s, const Request& r, int status, uint32_t views, double t_launch, double t_done) {
+  svd_request_done x;
+  memset(&x, 0, sizeof(x));
+  x.tag = r.tag;
+  x.status = status;
+  x.batch_views = views;
+  x.t_submit = r.t_submit;
+  x.t_launch = t_launch;
+  x.t_done = t_done;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->done.push_back(x);
+  if (status == SVD_OK) s->st.completed++;
+  else s->st.failed++;
+}
+
+static void unpin(svd_server* s, const std::vector<uint32_t>& slots) {
+  for (uint32_t sl : slots) s->pins[sl]--;
+}
+
+// Evict the least recently used resident slot that nobody pins; false if
+// there is none.
+static bool evict_one(svd_server* s) {
+  svd_world* w = s->w;
+  size_t best = SIZE_MAX;
+  for (size_t i = 0; i < w->slot.size(); i++) {
+    if (w->slot[i].state != svd_world::kResident || !w->slot[i].bytes || s->pins[i]) continue;
+    if (best == SIZE_MAX || s->last_use[i] < s->last_use[best]) best = i;
+  }
+  if (best == SIZE_MAX) return false;
+  const size_t bytes = w->slot[best].bytes;
+  if (world_evict_lods(w, (uint32_t)(best / 4), 1u << (best % 4), s->up) != SVD_OK) return false;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->data_bytes -= bytes;
+  s->st.evictions++;
+  s->st.evict_bytes += bytes;
+  s->st.pool_used = s->data_bytes;
+  return true;
+}
+
+// Make every slot of r resident and pinned.  `others` = launches or
+// already admitted requests hold pins, so waiting can free memory.  When
+// nothing else holds memory and the slots still do not fit (the free space is
+// fragmented), the pool is cleared and the view's slots are loaded into it
+// largest first.
+static int admit(svd_server* s, Request& r, bool others) {
+  svd_world* w = s->w;
+  if (!r.staged) {
+    const StageParams sp = world_stage_params(w, &r.frame, r.flags & SVD_NO_CULL, w->h_desc.data());
+    for (uint32_t ci = 0; ci < w->nchunks; ci++) {
+      const uint32_t v = host_stage_chunk(sp, ci);
+      if (!(v & (kViewCulled | kViewEmpty))) r.need.push_back(ci * 4 + (v & kViewLodMask));
+    }
+    r.staged = true;
+  }
+  bool uploaded = false;
+  int rc = SVD_OK;
+  for (int pass = 0; pass < 2; pass++) {
+    std::vector<uint32_t> pinned, miss;
+    for (uint32_t sl : r.need) {
+      if (w->slot[sl].state == svd_world::kResident) {
+        s->pins[sl]++;
+        pinned.push_back(sl);
+      } else {
+        miss.push_back(sl);
+      }
+    }
+    std::sort(miss.begin(), miss.end(), [&](uint32_t a, uint32_t b) {
+      const LodData& la = s->src[a / 4]->lod[a % 4];
+      const LodData& lb = s->src[b / 4]->lod[b % 4];
+      return la.off_end - la.off_begin > lb.off_end - lb.off_begin;
+    });
+    rc = SVD_OK;
+    for (uint32_t sl : miss) {
+      const uint32_t ci = sl / 4, k = sl % 4;
+      for (;;) {
+        rc = world_upload_lods(w, ci, s->src[ci], 1u << k, s->up);
+        if (rc != SVD_ENOMEM || !evict_one(s)) break;
+      }
+      if (rc) break;
+      s->pins[sl]++;
+      pinned.push_back(sl);
+      uploaded = true;
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->data_bytes += w->slot[sl].bytes;
+      s->st.uploads++;
+      s->st.upload_bytes += w->slot[sl].bytes;
+      s->st.pool_used = s->data_bytes;
+    }
+    if (rc == SVD_OK) break;
+    unpin(s, pinned);
+    if (rc != SVD_ENOMEM || others) break;
+    while (evict_one(s)) {  // nobody pins anything: start from an empty pool
+    }
+  }
+  if (uploaded) {  // every launch from now on waits for these copies
+    if (hipEventRecord(s->up_done, s->up) != hipSuccess) {
+      if (rc == SVD_OK) unpin(s, r.need);
+      return svd_fail(SVD_EDEVICE, "serve: upload event");
+    }
+    s->up_pending = true;
+  }
+  if (rc == SVD_ENOMEM) return others ? kWait : svd_fail(SVD_ENOMEM, "serve: the view needs more than the whole pool");
+  if (rc) return rc;
+  for (uint32_t sl : r.need) s->last_use[sl] = ++s->use_seq;
+  return kAdmitted;
+}
+
+static bool reap(svd_server* s) {
+  bool progress = false;
+  for (Flight& f : s->fl) {
+    if (!f.busy) continue;
+    const hipError_t e = hipEventQuery(f.done);
+    if (e == hipErrorNotReady) continue;
+    const double t = s->now();
+    const int status = e == hipSuccess ? SVD_OK : SVD_EDEVICE;
+    for (const Request& r : f.reqs) {
+      unpin(s, r.need);
+      finish(s, r, status, (uint32_t)f.reqs.size(), f.t_launch, t);
+    }
+    f.reqs.clear();
+    f.busy = false;
+    progress = true;
+  }
+  if (progress) s->done_cv.notify_all();
+  return progress;
+}
+
+static int enqueue(svd_server* s, Flight& f) {
+  if (s->up_pending && hipStreamWaitEvent(f.stream, s->up_done, 0) != hipSuccess)
+    return svd_fail(SVD_EDEVICE, "serve: stream wait");
+  int rc = SVD_OK;
+  if (f.batch) {
+    std::vector<svd_ray_frame> frames;
+    std::vector<svd_hit*> outs;
+    for (const Request& r : f.reqs) {
+      frames.push_back(r.frame);
+      outs.push_back(r.out);
+    }
+    rc = batch_enqueue(f.batch, frames.data(), outs.data(), (uint32_t)frames.size(), f.reqs[0].flags, f.stream);
+  } else {
+    rc = svd_trace_frame(s->w, &f.reqs[0].frame, f.reqs[0].out, f.reqs[0].flags, f.stream);
+  }
+  if (rc) return rc;
+  if (hipEventRecord(f.done, f.stream) != hipSuccess) return svd_fail(SVD_EDEVICE, "serve: launch event");
+  return SVD_OK;
+}
+
+static bool launch(svd_server* s) {
+  bool progress = false;
+  const uint32_t per_launch = s->d.mode == SVD_SERVE_BATCHED ? s->d.max_views : 1;
+  for (Flight& f : s->fl) {
+    if (f.busy) continue;
+    if (s->pending.empty()) break;
+    std::vector<Request> take;
+    uint64_t rays = 0;
+    while (!s->pending.empty() && take.size() < per_launch) {
+      Request& r = s->pending.front();
+      const uint64_t px = (uint64_t)r.frame.width * r.frame.height;
+      if (!take.empty() && (rays + px > s->d.max_rays || r.flags != take[0].flags)) break;
+      const int a = admit(s, r, !take.empty() || any_busy(s));
+      if (a == kWait) {
+        if (!r.waited) {
+          r.waited = true;
+          std::lock_guard<std::mutex> lk(s->mu);
+          s->st.memory_waits++;
+        }
+        break;
+      }
+      if (a != kAdmitted) {  // cannot be served: report and drop
+        finish(s, r, a, 0, 0, s->now());
+        s->pending.pop_front();
+        progress = true;
+        continue;
+      }
+      rays += px;
+      take.push_back(std::move(r));
+      s->pending.pop_front();
+    }
+    if (take.empty()) break;
+    f.reqs = std::move(take);
+    f.t_launch = s->now();
+    const int rc = enqueue(s, f);
+    if (rc) {
+      for (const Request& r : f.reqs) {
+        unpin(s, r.need);
+        finish(s, r, rc, 0, f.t_launch, s->now());
+      }
+      f.reqs.clear();
+    } else {
+      f.busy = true;
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->st.launches++;
+    }
+    progress = true;
+  }
+  if (progress) s->done_cv.notify_all();
+  return progress;
+}
+
+static void worker(svd_server* s) {
+  hipSetDevice(s->device);
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      while (!s->inbox.empty()) {
+        s->pending.push_back(std::move(s->inbox.front()));
+        s->inbox.pop_front();
+      }
+      if (s->pending.empty() && !any_busy(s)) {
+        if (s->stop) break;
+        s->wake.wait(lk, [s] { return s->stop || !s->inbox.empty(); });
+        continue;
+      }
+    }
+    const bool a = reap(s);
+    const bool b = launch(s);
+    if (!a && !b) std::this_thread::yield();  // launches in flight: poll their events
+  }
+}
+
+static void server_release(svd_server* s) {
+  for (Flight& f : s->fl) {
+    if (f.batch) svd_batch_destroy(f.batch);
+    if (f.done) hipEventDestroy(f.done);
+    if (f.stream && f.stream != s->plain) hipStreamDestroy(f.stream);
+  }
+  if (s->plain) hipStreamDestroy(s->plain);
+  if (s->up_done) hipEventDestroy(s->up_done);
+  if (s->up) hipStreamDestroy(s->up);
+  delete s;
+}
+
+extern "C" int svd_server_create(svd_world* w, const svd_server_desc* d, svd_server** out) {
+  if (!w || !d || !out) return svd_fail(SVD_EINVAL, "svd_server_create: null argument");
+  *out = nullptr;
+  if (d->mode != SVD_SERVE_BATCHED && d->mode != SVD_SERVE_PLAIN) return svd_fail(SVD_EINVAL, "serve: unknown mode");
+  if (d->inflight < 1 || d->inflight > 8) return svd_fail(SVD_EINVAL, "serve: inflight must be 1..8");
+  if (d->mode == SVD_SERVE_BATCHED && (d->max_views < 1 || d->max_views > 1024 || d->max_rays < 1))
+    return svd_fail(SVD_EINVAL, "serve: max_views must be 1..1024 and max_rays >= 1");
+  svd_server* s = new (std::nothrow) svd_server();
+  if (!s) return svd_fail(SVD_ENOMEM, "serve: out of host memory");
+  s->w = w;
+  s->d = *d;
+  s->t0 = Clock::now();
+  memset(&s->st, 0, sizeof(s->st));
+  for (const svd_world::Slot& sl : w->slot)
+    if (sl.state == svd_world::kResident) s->data_bytes += sl.bytes;
+  s->st.pool_used = s->data_bytes;
+  s->src.assign(w->nchunks, nullptr);
+  s->pins.assign(w->slot.size(), 0);
+  s->last_use.assign(w->slot.size(), 0);
+  hipError_t e = hipGetDevice(&s->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->up, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->up_done, hipEventDisableTiming);
+  if (e == hipSuccess && d->mode == SVD_SERVE_PLAIN) e = hipStreamCreateWithFlags(&s->plain, hipStreamNonBlocking);
+  s->fl.resize(d->inflight);
+  for (Flight& f : s->fl) {
+    if (e != hipSuccess) break;
+    if (d->mode == SVD_SERVE_PLAIN) f.stream = s->plain;
+    else e = hipStreamCreateWithFlags(&f.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&f.done, hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    server_release(s);
+    return svd_fail(SVD_EDEVICE, "serve: %s", hipGetErrorString(e));
+  }
+  if (d->mode == SVD_SERVE_BATCHED) {
+    for (Flight& f : s->fl) {
+      int rc = svd_batch_create(w, d->max_views, &f.batch);
+      if (rc == SVD_OK && d->tile_w) rc = svd_batch_set_tiling(f.batch, d->tile_w, d->claim ? d->claim : 1);
+      if (rc == SVD_OK && d->blocks_per_cu) rc = svd_batch_set_occupancy(f.batch, d->blocks_per_cu);
+      if (rc) {
+        server_release(s);
+        return rc;
+      }
+    }
+  }
+  s->th = std::thread(worker, s);
+  *out = s;
+  return SVD_OK;
+}
+
+extern "C" int svd_server_set_chunk(svd_server* s, const uint32_t c[3], const svd_blob* b) {
+  if (!s || !c || !b) return svd_fail(SVD_EINVAL, "svd_server_set_chunk: null argument");
+  svd_world* w = s->w;
+  for (int a = 0; a < 3; a++)
+    if (c[a] >= w->desc.grid[a]) return svd_fail(SVD_EINVAL, "serve: chunk outside the grid");
+  const uint32_t ci = c[0] + w->desc.grid[0] * (c[1] + w->desc.grid[1] * c[2]);
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->started) return svd_fail(SVD_EINVAL, "serve: chunk sources are fixed once requests arrive");
+  const int rc = world_upload_lods(w, ci, b, 0, s->up);  // describe only
+  if (rc) return rc;
+  if (!s->src[ci]) s->sources++;
+  s->src[ci] = b;
+  return SVD_OK;
+}
+
+extern "C" int svd_server_submit(svd_server* s, const svd_camera* cam, svd_hit* out_dev, uint32_t flags,
+                                 uint64_t tag) {
+  if (!s || !cam || !out_dev) return svd_fail(SVD_EINVAL, "svd_server_submit: null argument");
+  if (flags & ~SVD_NO_CULL) return svd_fail(SVD_EINVAL, "serve: unknown flags");
+  Request r;
+  int rc = svd_camera_frame(cam, &r.frame);
+  if (rc) return rc;
+  rc = check_frame(&r.frame);
+  if (rc) return rc;
+  r.tag = tag;
+  r.out = out_dev;
+  r.flags = flags;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop) return svd_fail(SVD_EINVAL, "serve: server is stopping");
+  if (s->sources != s->w->nchunks)
+    return svd_fail(SVD_EINVAL, "serve: %u of %u chunks have no source", s->w->nchunks - s->sources, s->w->nchunks);
+  if (!s->started) {
+    s->started = true;
+    hipStreamSynchronize(s->up);  // chunk descriptions are on the device before any launch
+  }
+  r.t_submit = s->now();
+  s->inbox.push_back(std::move(r));
+  s->st.submitted++;
+  s->wake.notify_one();
+  return SVD_OK;
+}
+
+extern "C" int svd_server_poll(svd_server* s, svd_request_done* out, uint32_t max, uint32_t* n, uint32_t wait_us) {
+  if (!s || !n || (max && !out)) return svd_fail(SVD_EINVAL, "svd_server_poll: null argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->done.empty() && wait_us)
+    s->done_cv.wait_for(lk, std::chrono::microseconds(wait_us), [s] { return !s->done.empty(); });
+  uint32_t k = 0;
+  while (k < max && !s->done.empty()) {
+    out[k++] = s->done.front();
+    s->done.pop_front();
+  }
+  *n = k;
+  return SVD_OK;
+}
+
+extern "C" int svd_server_stats_get(svd_server* s, svd_server_stats* st) {
+  if (!s || !st) return svd_fail(SVD_EINVAL, "svd_server_stats_get: null argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  *st = s->st;
+  return SVD_OK;
+}
+
+extern "C" void svd_server_destroy(svd_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->wake.notify_one();
+  if (s->th.joinable()) s->th.join();
+  server_release(s);
+}

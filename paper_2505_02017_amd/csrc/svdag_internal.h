@@ -2,7 +2,11 @@
 // libsvdag.  Nothing here is part of the public ABI (include/svdag.h).
 #pragma once
 
+#include <hip/hip_runtime_api.h>
+
+#include <cstddef>
 #include <cstdint>
+#include <map>
 #include <vector>
 
 #include "svdag.h"
@@ -42,6 +46,7 @@ constexpr uint32_t kPtrMask = (1u << kPtrBits) - 1;
 constexpr uint32_t kViewLodMask = 3u;
 constexpr uint32_t kViewCulled = 4u;
 constexpr uint32_t kViewEmpty = 8u;
+constexpr uint32_t kViewMissing = 16u;  // needed, but its DAG is not resident (nodes == 0)
 
 struct LodData {
   uint32_t R = 0;
@@ -94,7 +99,7 @@ struct StageParams {
 struct alignas(256) BatchView {
   int64_t O[3], A[3], BX[3], BY[3];
   int64_t n[4][3];        // cull planes (zero = none)
-  uint64_t out_offset;    // first record of this view in the batch output
+  uint64_t out;           // device address of this view's first record
   uint32_t W, H;
   uint32_t tiles_x;       // tiles per image row
   uint32_t tile_base;     // first global tile index of this view
@@ -105,13 +110,12 @@ static_assert(sizeof(BatchView) == 256, "BatchView must stay 256 bytes");
 // Batch header (device memory): rewritten by each svd_batch_trace call, so
 // that one captured graph serves every batch.
 struct alignas(64) BatchHeader {
-  uint64_t out;           // device address of the batch's svd_hit records
   uint32_t nviews;
   uint32_t total_tiles;
   uint32_t next_tile;     // work-queue head (reset by a kernel, not a memset)
   uint32_t tile_w;        // tile width in pixels (tile = tile_w x 64/tile_w)
   uint32_t claim;         // tiles a wave takes per queue access
-  uint32_t pad[9];
+  uint32_t pad[11];
 };
 static_assert(sizeof(BatchHeader) == 64, "BatchHeader must stay 64 bytes");
 
@@ -134,6 +138,7 @@ int check_frame(const svd_ray_frame* f);
 
 // kernels.hip
 int launch_chunk_stage(const StageParams& p, void* stream);
+uint32_t host_stage_chunk(const StageParams& p, uint32_t ci);  // the stage's decision, on the host
 int launch_trace(const TraceParams& p, uint32_t blocks, void* stream);
 int trace_occupancy(uint32_t* blocks_per_cu);
 int launch_set_desc(DevDag* dst, const DevDag* src4, uint32_t n, void* stream);
@@ -152,3 +157,115 @@ struct svd_blob {
 
 // Thread-local error message; returns `code` for convenient `return fail(...)`.
 int svd_fail(int code, const char* fmt, ...);
+
+// Default persistent grid of the per-view trace.  Fewer resident waves than
+// fit a CU trace 1440p views faster (blocks per CU 6 / 5 / 4 / 3: 3.87 /
+// 4.07 / 4.21 / 4.16 Grays/s on the 16x16-chunk map; contention of more
+// resident rays for the CU's cache is the likely cause).
+constexpr uint32_t kViewBlocksPerCu = 4;
+
+// A world: the device descriptor table, the per-view table and queue, and a
+// first-fit sub-allocator over the rest of the caller's pool.  Residency is
+// kept per (chunk, LOD) slot:
+//   absent     nothing known (a plain trace refuses to run while any is);
+//   described  the blob's box and solid count are in the descriptor, but no
+//              DAG (addresses zero): a view that needs it gets records
+//              marked "not loaded" instead of reading it;
+//   resident   the LOD's device image is in the pool.
+struct svd_world {
+  enum : uint8_t { kAbsent = 0, kDescribed = 1, kResident = 2 };
+  struct Slot {
+    size_t off = 0, bytes = 0;
+    uint8_t state = kAbsent;
+  };
+  svd_world_desc desc;
+  uint32_t nchunks = 0;
+  uint8_t* pool = nullptr;
+  size_t pool_bytes = 0;
+  svd::DevDag* d_desc = nullptr;
+  uint32_t* d_view = nullptr;
+  uint32_t* d_queue = nullptr;  // per-view trace work queue (256-byte control block)
+  uint32_t cus = 0;             // compute units of the device
+  uint32_t max_per_cu = 0;      // resident trace blocks per CU at full occupancy
+  uint32_t per_cu = 0;          // trace blocks per CU in use (persistent grid = per_cu x cus)
+  size_t data_begin = 0;
+  std::map<size_t, size_t> free_blocks;  // offset -> bytes
+  std::vector<Slot> slot;                // [chunk * 4 + lod]
+  std::vector<svd::DevDag> h_desc;       // host copy of the device descriptor table
+  uint32_t absent = 0;                   // absent slots with lod < lod_count
+  size_t used = 0;
+  svd_ray_frame staged;  // frame of the last chunk stage (its view table)
+  bool has_staged = false;
+
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = (bytes + 255) / 256 * 256;
+    for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t roff = it->first + bytes;
+      free_blocks.erase(it);
+      if (rest) free_blocks[roff] = rest;
+      used += bytes;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = (bytes + 255) / 256 * 256;
+    used -= bytes;
+    auto it = free_blocks.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_blocks.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_blocks.erase(nx);
+    }
+    if (it != free_blocks.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_blocks.erase(it);
+      }
+    }
+  }
+};
+
+// Stage parameters of a frame over the world (cull planes unless no_cull),
+// with `desc` pointing at the given table (device or host copy).
+svd::StageParams world_stage_params(const svd_world* w, const svd_ray_frame* f, bool no_cull,
+                                    const svd::DevDag* desc);
+// Make LODs `mask` of chunk ci resident from b and describe the others from b
+// (descriptor writes on `stream`); all or nothing (SVD_ENOMEM if the pool has
+// no room).  Evict: LODs `mask` go back to described (descriptor writes on
+// `stream`), their memory to the pool.
+int world_upload_lods(svd_world* w, uint32_t ci, const svd_blob* b, uint32_t mask, hipStream_t stream);
+int world_evict_lods(svd_world* w, uint32_t ci, uint32_t mask, hipStream_t stream);
+
+// A batch: device memory from the world's pool,
+//   [BatchHeader 64 B | pad to 256][BatchView x max_views][view tables: max_views x nchunks u32],
+// pinned host staging (header + views) guarded by an event, and the captured
+// graph (reset + stage + persistent trace) that every launch replays.
+struct svd_batch {
+  svd_world* w = nullptr;
+  uint32_t max_views = 0;
+  size_t off = 0, bytes = 0;
+  svd::BatchHeader* d_hdr = nullptr;
+  svd::BatchView* d_views = nullptr;
+  uint32_t* d_tables = nullptr;
+  uint8_t* h_stage = nullptr;      // pinned: header + views
+  size_t stage_bytes = 0;
+  hipEvent_t staged = nullptr;     // the last upload of h_stage has been consumed
+  hipEvent_t finished = nullptr;   // the last graph launch has completed
+  bool stage_pending = false;
+  bool launched = false;
+  hipStream_t cap = nullptr;       // capture stream (default priority)
+  hipGraphExec_t exec = nullptr;
+  uint32_t cus = 0, max_per_cu = 0, per_cu = 0;  // persistent grid = per_cu x cus blocks
+  uint32_t tile_w = 8, claim = 1;
+};
+
+// Enqueue a batch whose view v writes its records at outs[v] (validated
+// like svd_batch_trace_frames, except the capacity of each output, which is
+// the caller's).
+int batch_enqueue(svd_batch* b, const svd_ray_frame* frames, svd_hit* const* outs, uint32_t n, uint32_t flags,
+                  hipStream_t stream);

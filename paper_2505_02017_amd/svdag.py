@@ -24,6 +24,7 @@ SVD_ERANGE = -5
 SVD_ENOTFOUND = -6
 SVD_NO_CULL = 1
 FAULT_CHUNK = 0xFFFFFFFE  # written by the trace if its iteration guard fires
+CHUNK_NOT_LOADED = 0xFFFFFFFD  # a ray reached a chunk whose picked LOD is only described
 
 _NAMES = {SVD_EINVAL: "EINVAL", SVD_ENOMEM: "ENOMEM", SVD_EDEVICE: "EDEVICE",
           SVD_EFORMAT: "EFORMAT", SVD_ERANGE: "ERANGE", SVD_ENOTFOUND: "ENOTFOUND"}
@@ -32,11 +33,13 @@ EXPORTS = [
     "svd_last_error", "svd_chunk_build", "svd_blob_to_bytes", "svd_blob_from_bytes",
     "svd_blob_free", "svd_free", "svd_blob_stats_get", "svd_blob_canonical",
     "svd_world_create", "svd_world_destroy", "svd_world_pool_used", "svd_chunk_upload",
-    "svd_chunk_evict", "svd_camera_frame", "svd_trace_view", "svd_trace_frame",
+    "svd_chunk_evict", "svd_chunk_upload_lods", "svd_chunk_evict_lods", "svd_camera_frame", "svd_trace_view", "svd_trace_frame",
     "svd_view_stage", "svd_view_trace", "svd_view_table",
     "svd_world_set_occupancy", "svd_world_get_occupancy",
     "svd_batch_create", "svd_batch_destroy", "svd_batch_trace", "svd_batch_trace_frames",
     "svd_batch_set_tiling", "svd_batch_set_occupancy", "svd_batch_get_tiling", "svd_batch_tune",
+    "svd_server_create", "svd_server_set_chunk", "svd_server_submit", "svd_server_poll",
+    "svd_server_stats_get", "svd_server_destroy",
 ]
 
 
@@ -61,6 +64,23 @@ class svd_ray_frame(ctypes.Structure):
     _fields_ = [("O", ctypes.c_int64 * 3), ("A", ctypes.c_int64 * 3),
                 ("BX", ctypes.c_int64 * 3), ("BY", ctypes.c_int64 * 3),
                 ("G", ctypes.c_int32), ("width", ctypes.c_uint32), ("height", ctypes.c_uint32)]
+
+
+class svd_server_desc(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_uint32), ("max_views", ctypes.c_uint32), ("inflight", ctypes.c_uint32),
+                ("tile_w", ctypes.c_uint32), ("claim", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
+                ("max_rays", ctypes.c_uint64)]
+
+
+class svd_request_done(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("batch_views", ctypes.c_uint32),
+                ("t_submit", ctypes.c_double), ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class svd_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "submitted", "completed", "failed", "launches", "uploads", "upload_bytes", "evictions",
+        "evict_bytes", "memory_waits", "pool_used")]
 
 
 class svd_blob_stats(ctypes.Structure):
@@ -99,6 +119,8 @@ def lib() -> ctypes.CDLL:
         L.svd_world_pool_used.argtypes = [vp, ctypes.POINTER(sz)]
         L.svd_chunk_upload.argtypes = [vp, ctypes.POINTER(u32), vp, vp]
         L.svd_chunk_evict.argtypes = [vp, ctypes.POINTER(u32)]
+        L.svd_chunk_upload_lods.argtypes = [vp, ctypes.POINTER(u32), vp, u32, vp]
+        L.svd_chunk_evict_lods.argtypes = [vp, ctypes.POINTER(u32), u32, vp]
         L.svd_camera_frame.argtypes = [ctypes.POINTER(svd_camera), ctypes.POINTER(svd_ray_frame)]
         L.svd_trace_view.argtypes = [vp, ctypes.POINTER(svd_camera), vp, u32, vp]
         L.svd_trace_frame.argtypes = [vp, ctypes.POINTER(svd_ray_frame), vp, u32, vp]
@@ -118,9 +140,16 @@ def lib() -> ctypes.CDLL:
         L.svd_batch_get_tiling.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32)]
         L.svd_batch_tune.argtypes = [vp, ctypes.POINTER(svd_camera), u32, vp, u64, u32, vp,
                                      ctypes.POINTER(ctypes.c_float)]
+        L.svd_server_create.argtypes = [vp, ctypes.POINTER(svd_server_desc), ctypes.POINTER(vp)]
+        L.svd_server_set_chunk.argtypes = [vp, ctypes.POINTER(u32), vp]
+        L.svd_server_submit.argtypes = [vp, ctypes.POINTER(svd_camera), vp, u32, u64]
+        L.svd_server_poll.argtypes = [vp, ctypes.POINTER(svd_request_done), u32, ctypes.POINTER(u32), u32]
+        L.svd_server_stats_get.argtypes = [vp, ctypes.POINTER(svd_server_stats)]
+        L.svd_server_destroy.argtypes = [vp]
+        L.svd_server_destroy.restype = None
         for n in EXPORTS:
             if n not in ("svd_last_error", "svd_blob_free", "svd_free", "svd_world_destroy",
-                         "svd_batch_destroy"):
+                         "svd_batch_destroy", "svd_server_destroy"):
                 getattr(L, n).restype = i32
         _lib = L
     return _lib
@@ -230,6 +259,11 @@ def table_bytes(grid) -> int:
     return n * 4 * 64 + (n * 4 + 255) // 256 * 256 + 256
 
 
+def batch_bytes(nchunks: int, max_views: int) -> int:
+    """Pool bytes a batch of max_views views takes (see svd_batch_create)."""
+    return 256 + 256 * max_views + (max_views * nchunks * 4 + 255) // 256 * 256
+
+
 class World:
     """A device world over a caller-owned pool tensor (torch uint8, on a GPU)."""
 
@@ -284,6 +318,15 @@ def svd_chunk_upload(w: World, c, b: Blob, stream=None):
 def svd_chunk_evict(w: World, c):
     _check(lib().svd_chunk_evict(w.ptr, _c3(c)))
     w._blobs.pop(tuple(int(v) for v in c), None)
+
+
+def svd_chunk_upload_lods(w: World, c, b: Blob, lod_mask: int, stream=None):
+    _check(lib().svd_chunk_upload_lods(w.ptr, _c3(c), b.ptr, lod_mask, _stream_ptr(stream)))
+    w._blobs[tuple(int(v) for v in c)] = b
+
+
+def svd_chunk_evict_lods(w: World, c, lod_mask: int, stream=None):
+    _check(lib().svd_chunk_evict_lods(w.ptr, _c3(c), lod_mask, _stream_ptr(stream)))
 
 
 def to_camera(cam) -> svd_camera:
@@ -445,6 +488,72 @@ def svd_batch_tune(b: Batch, cams, out, reps: int = 3, stream=None):
                                 ctypes.byref(ms)))
     tw, cl, oc = svd_batch_get_tiling(b)
     return tw, cl, oc, ms.value
+
+
+# ------------------------------------------------------------------ serving
+
+SVD_SERVE_BATCHED = 0
+SVD_SERVE_PLAIN = 1
+
+
+class Server:
+    """A request server over a world (see svd_server_create).  Keeps the
+    world and the chunk source blobs alive while it lives."""
+
+    def __init__(self, ptr: int, world: World):
+        self._p = ctypes.c_void_p(ptr)
+        self.world = world
+        self._sources = {}
+        self._free = lib().svd_server_destroy
+
+    @property
+    def ptr(self):
+        return self._p
+
+    def __del__(self):
+        if getattr(self, "_p", None) and self._p.value:
+            self._free(self._p)
+            self._p = None
+
+
+def svd_server_create(w: World, mode: int = SVD_SERVE_BATCHED, max_views: int = 64, inflight: int = 2,
+                      max_rays: int = 1 << 24, tile_w: int = 0, claim: int = 0, blocks_per_cu: int = 0) -> Server:
+    d = svd_server_desc(mode=mode, max_views=max_views, inflight=inflight, tile_w=tile_w, claim=claim,
+                        blocks_per_cu=blocks_per_cu, max_rays=max_rays)
+    out = ctypes.c_void_p()
+    _check(lib().svd_server_create(w.ptr, ctypes.byref(d), ctypes.byref(out)))
+    return Server(out.value, w)
+
+
+def svd_server_set_chunk(s: Server, c, b: Blob):
+    _check(lib().svd_server_set_chunk(s.ptr, _c3(c), b.ptr))
+    s._sources[tuple(int(v) for v in c)] = b
+
+
+def svd_server_submit(s: Server, cam, out, tag: int, flags: int = 0):
+    c = cam if isinstance(cam, svd_camera) else to_camera(cam)
+    _check(lib().svd_server_submit(s.ptr, ctypes.byref(c), _out_ptr(out, c.width * c.height), flags, tag))
+
+
+def svd_server_poll(s: Server, max_n: int = 256, wait_us: int = 0) -> list:
+    """Finished requests: list of dicts (tag, status, batch_views, t_submit,
+    t_launch, t_done; seconds on the server's clock)."""
+    arr = (svd_request_done * max_n)()
+    n = ctypes.c_uint32()
+    _check(lib().svd_server_poll(s.ptr, arr, max_n, ctypes.byref(n), wait_us))
+    return [{k: getattr(arr[i], k) for k, _ in svd_request_done._fields_} for i in range(n.value)]
+
+
+def svd_server_stats_get(s: Server) -> dict:
+    st = svd_server_stats()
+    _check(lib().svd_server_stats_get(s.ptr, ctypes.byref(st)))
+    return {k: int(getattr(st, k)) for k, _ in svd_server_stats._fields_}
+
+
+def svd_server_destroy(s: Server):
+    if s._p and s._p.value:
+        lib().svd_server_destroy(s._p)
+        s._p = None
 
 
 # ------------------------------------------------------------------ records
