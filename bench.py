@@ -98,6 +98,18 @@ def main():
     ap.add_argument("--batch-views", type=int, default=64,
                     help="views in the batched-launch comparison (0 = skip it)")
     ap.add_argument("--batch-reps", type=int, default=10)
+    ap.add_argument("--serve-seconds", type=float, default=8.0,
+                    help="length of each fixed-rate serving run (0 = skip the served comparison)")
+    ap.add_argument("--serve-rates", default="200,2000", help="request arrival rates (req/s)")
+    ap.add_argument("--serve-backlog", type=int, default=1000,
+                    help="requests of the saturated run (as many in flight as output buffers)")
+    ap.add_argument("--serve-pool-frac", type=float, default=0.25,
+                    help="server pool for chunk data, as a fraction of the map's device bytes")
+    ap.add_argument("--serve-views", type=int, default=64, help="requests per batched launch")
+    ap.add_argument("--serve-inflight", type=int, default=2, help="launches in flight")
+    ap.add_argument("--serve-max-rays", type=int, default=8 << 20, help="rays per batched launch")
+    ap.add_argument("--serve-speed", type=float, default=600.0,
+                    help="walker speed, voxels/s (fast enough that the walkers' chunk sets outgrow the pool)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -303,6 +315,8 @@ def main():
 
     if args.batch_views > 0:
         result["batched"] = bench_batched(args, sw, world, svdag, torch)
+    if args.serve_seconds > 0:
+        result["served"] = bench_served(args, sw, blobs, lod_count, thr, world, svdag, torch)
 
     print(json.dumps(result), flush=True)
 
@@ -366,6 +380,120 @@ def bench_batched(args, sw, world, svdag, torch):
         "plain_ms_p99": round(float(np.percentile(mp, 99)), 4),
         "identical_to_plain": identical,
     }
+
+
+def bench_served(args, sw, blobs, lod_count, thr, full_world, svdag, torch):
+    """Served requests over a pool that holds a fraction of the map's chunk
+    LODs: walkers issue Poisson-arriving views of mixed resolution; batched
+    continuous serving against per-request plain launches on the same
+    schedule, at fixed rates and saturated (as many requests in flight as
+    there are output buffers).  Latency = completion seen by the server's
+    worker minus the request's scheduled arrival."""
+    import threading
+    gx, gy, gz = sw.grid
+    nch = gx * gy * gz
+    CL = sw.chunk_log2
+    coords = [(ci % gx, (ci // gx) % gy, ci // (gx * gy)) for ci in range(nch)]
+    all_bytes = sum((svdag.svd_blob_stats_get(b, k)["device_bytes"] + 255) // 256 * 256
+                    for b in blobs.values() for k in range(lod_count))
+    budget = int(args.serve_pool_frac * all_bytes) // 256 * 256
+    ring, maxpx = 256, 1920 * 1080
+    outs = torch.empty((ring, maxpx, 4), dtype=torch.int32, device="cuda")
+    desc = svdag.make_desc(CL, sw.grid, lod_count, thr)
+    views, inflight = args.serve_views, args.serve_inflight
+    rates = [float(r) for r in args.serve_rates.split(",") if r]
+    old_switch = sys.getswitchinterval()
+    sys.setswitchinterval(0.0005)
+
+    def run(mode, schedule, backlog):
+        pool = torch.empty(svdag.table_bytes(sw.grid) + inflight * svdag.batch_bytes(nch, views) + budget,
+                           dtype=torch.uint8, device="cuda")
+        w = svdag.svd_world_create(desc, pool)
+        s = svdag.svd_server_create(w, mode=mode, max_views=views, inflight=inflight,
+                                    max_rays=args.serve_max_rays)
+        for ci, b in blobs.items():
+            svdag.svd_server_set_chunk(s, coords[ci], b)
+        torch.cuda.synchronize()
+        n = len(schedule)
+        late = np.zeros(n)
+        busy = np.zeros(ring, bool)
+        cv = threading.Condition()
+        done = {}
+
+        def submitter():
+            t0 = time.perf_counter()
+            for i, (t, cam) in enumerate(schedule):
+                j = i % ring
+                with cv:
+                    while busy[j]:
+                        cv.wait(0.01)
+                    busy[j] = True
+                if not backlog:
+                    target = t0 + t
+                    while True:
+                        d = target - time.perf_counter()
+                        if d <= 0:
+                            break
+                        if d > 0.001:
+                            time.sleep(d - 0.0008)
+                    late[i] = time.perf_counter() - target
+                svdag.svd_server_submit(s, cam, outs[j], tag=i)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        while len(done) < n:
+            for d in svdag.svd_server_poll(s, 1024, wait_us=20000):
+                done[d["tag"]] = d
+                with cv:
+                    busy[d["tag"] % ring] = False
+                    cv.notify_all()
+        th.join()
+        st = svdag.svd_server_stats_get(s)
+        svdag.svd_server_destroy(s)
+        torch.cuda.synchronize()
+        failed = sum(1 for d in done.values() if d["status"] != 0)
+        lat = np.array([done[i]["t_done"] - done[i]["t_submit"] + late[i] for i in range(n)]) * 1e3
+        warm = np.array([t >= 1.0 for t, _ in schedule]) if not backlog else np.ones(n, bool)
+        rays = sum(c.width * c.height for _, c in schedule)
+        span = max(d["t_done"] for d in done.values()) - min(d["t_submit"] for d in done.values())
+        bv = np.array([d["batch_views"] for d in done.values()])
+        r = {"requests": n, "failed": failed, "grays": round(rays / span / 1e9, 4),
+             "p50_ms": round(float(np.percentile(lat[warm], 50)), 3),
+             "p99_ms": round(float(np.percentile(lat[warm], 99)), 3),
+             "mean_requests_per_launch": round(float(bv.mean()), 2), "launches": st["launches"],
+             "uploads": st["uploads"], "upload_mib": round(st["upload_bytes"] / 2**20, 1),
+             "evictions": st["evictions"], "memory_waits": st["memory_waits"]}
+        # the last requests' records are still in the output ring: each equals its view traced alone
+        ok = True
+        for i in range(max(0, n - 8), n):
+            cam = schedule[i][1]
+            alone = torch.empty((cam.width * cam.height, 4), dtype=torch.int32, device="cuda")
+            svdag.svd_trace_view(full_world, svdag.to_camera(cam), alone)
+            torch.cuda.synchronize()
+            ok &= bool(torch.equal(alone, outs[i % ring, :cam.width * cam.height]))
+        r["last8_identical_to_alone"] = ok
+        return r
+
+    res = {"pool_bytes_for_chunks": budget, "map_bytes_all_lods": all_bytes,
+           "pool_fraction": args.serve_pool_frac, "walkers": 8, "walker_speed": args.serve_speed,
+           "resolutions": "uniform over 320x180, 640x360, 1280x720, 1920x1080",
+           "batched_launch": {"max_requests": views, "max_rays": args.serve_max_rays, "inflight": inflight},
+           "latency": "scheduled arrival to completion; requests arriving in the first second "
+                      "(cold pool) are served but not in the percentiles"}
+    modes = (("batched", svdag.SVD_SERVE_BATCHED), ("plain", svdag.SVD_SERVE_PLAIN))
+    for rate in rates:
+        sched = sw.walk_requests(8, rate, args.serve_seconds, seed=int(rate), speed=args.serve_speed)
+        for name, mode in modes:
+            log(f"serving {len(sched)} requests at {rate:g}/s, {name}")
+            res[f"{name}_{rate:g}rps"] = run(mode, sched, False)
+    sched = sw.walk_requests(8, 400.0, args.serve_backlog / 400.0 + 1.0, seed=99,
+                             speed=args.serve_speed)[:args.serve_backlog]
+    for name, mode in modes:
+        log(f"serving {len(sched)} requests saturated, {name}")
+        res[f"{name}_saturated"] = run(mode, sched, True)
+    sys.setswitchinterval(old_switch)
+    del outs
+    return res
 
 
 if __name__ == "__main__":

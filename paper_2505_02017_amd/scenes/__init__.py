@@ -190,6 +190,52 @@ class SceneWorld:
         return cams
 
 
+    def walk_requests(self, walkers: int, rate: float, duration: float, seed: int,
+                      sizes=((320, 180), (640, 360), (1280, 720), (1920, 1080)),
+                      speed: float = 150.0, height_above: float = 50.0):
+        """Seeded serving load: Poisson arrivals (mean gap 1/rate seconds) over
+        `duration` seconds; each request is a view from one of `walkers`
+        cameras that wander the map at `speed` voxels/s, `height_above`
+        voxels over the terrain, heading changing every second, looking
+        roughly ahead with pitch in [-20, 5] degrees; resolution uniform over
+        `sizes`.  Returns [(arrival_s, Camera)]."""
+        rng = np.random.default_rng([self.seed, seed, 0x5E12])
+        X, Y, Z = self.extent
+        margin = min(256.0, X / 8, Y / 8)
+        dt = 0.05
+        steps = int(math.ceil(duration / dt)) + 2
+        pos = np.empty((walkers, steps, 2))
+        head = np.empty((walkers, steps))
+        for w in range(walkers):
+            p = np.array([rng.uniform(margin, X - margin), rng.uniform(margin, Y - margin)])
+            h = rng.uniform(0, 2 * math.pi)
+            for i in range(steps):
+                if i and i % int(round(1 / dt)) == 0:
+                    h += rng.normal(0, 0.6)
+                p = p + speed * dt * np.array([math.cos(h), math.sin(h)])
+                for a, hi in ((0, X), (1, Y)):  # reflect at the map's margin
+                    if p[a] < margin or p[a] > hi - margin:
+                        p[a] = min(max(p[a], margin), hi - margin)
+                        h = math.pi - h if a == 0 else -h
+                pos[w, i], head[w, i] = p, h
+        out, t = [], 0.0
+        while True:
+            t += rng.exponential(1.0 / rate)
+            if t >= duration:
+                break
+            w = int(rng.integers(walkers))
+            i = min(int(t / dt), steps - 1)
+            x, y = pos[w, i]
+            z = min(self.height(int(x), int(y)) + height_above, Z - 0.5)
+            yaw = head[w, i] + rng.uniform(-0.3, 0.3)
+            pitch = math.radians(rng.uniform(-20.0, 5.0))
+            W, H = sizes[int(rng.integers(len(sizes)))]
+            d = np.array([math.cos(pitch) * math.cos(yaw), math.cos(pitch) * math.sin(yaw), math.sin(pitch)])
+            cam = Camera((x, y, z), tuple(np.array([x, y, z]) + 100.0 * d), (0.0, 0.0, 1.0), 60.0, W, H)
+            out.append((t, cam.as_f32()))
+        return out
+
+
 # -- tiny random worlds (tests) -------------------------------------------
 
 def random_grid(rng: np.random.Generator, R: int, fill: float, nmat: int = 15,
