@@ -91,6 +91,7 @@ def main():
     ap.add_argument("--workload", default="map512", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=2025)
     ap.add_argument("--views", type=int, default=10)
+    ap.add_argument("--beam", action="store_true", help="trace with the beam pass (same records)")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle legs (CPU baseline and visit counts)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-baseline time")
@@ -196,21 +197,26 @@ def main():
     out = torch.empty((W * H, 4), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
 
+    stage_flags = svdag.SVD_BEAM if args.beam else 0
+
     def step(i, ev=None):
         f = frames_gpu[i % len(frames_gpu)]
         if ev is not None:
             ev[0].record(stream)
-        svdag.svd_view_stage(world, f, 0, stream)
+        svdag.svd_view_stage(world, f, stage_flags, stream)
         if ev is not None:
             ev[1].record(stream)
-        svdag.svd_view_trace(world, f, out, stream)
+        svdag.svd_view_beam(world, f, out, stream)
         if ev is not None:
             ev[2].record(stream)
+        svdag.svd_view_trace(world, f, out, stream)
+        if ev is not None:
+            ev[3].record(stream)
 
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
@@ -218,8 +224,10 @@ def main():
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     stage_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
-    trace_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
-    view_ms = stage_ms + trace_ms
+    beam_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
+    trace_ms = np.array([e[2].elapsed_time(e[3]) for e in evs])
+    view_ms = stage_ms + beam_ms + trace_ms
+    pass_ms = beam_ms + trace_ms  # the trace pass: beam kernel + trace kernel
     rays = W * H * args.steps
     value = rays / t_total / 1e9
 
@@ -245,7 +253,9 @@ def main():
         "p50_view_ms": round(float(np.percentile(view_ms, 50)), 4),
         "p99_view_ms": round(float(np.percentile(view_ms, 99)), 4),
         "trace_kernel_ms_mean": round(float(trace_ms.mean()), 4),
+        "beam_kernel_ms_mean": round(float(beam_ms.mean()), 4),
         "stage_kernel_ms_mean": round(float(stage_ms.mean()), 4),
+        "beam_pass": bool(args.beam),
         "hit_fraction": round(float(hits["hit"].mean()), 4),
     }
 
@@ -263,20 +273,21 @@ def main():
         view_b = np.array([p.mean() for p in per_ray])
         launches = np.bincount(np.arange(args.steps) % nviews, minlength=nviews)
         bytes_per_launch = float((view_b * launches).sum() / launches.sum()) * W * H
-        achieved = bytes_per_launch / (trace_ms.mean() * 1e-3) / 1e9
+        achieved = bytes_per_launch / (pass_ms.mean() * 1e-3) / 1e9
         prof = counter_profile(args.workload)
         traffic = float(prof["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in prof else None
         result["roofline"] = {
             "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5),
             "traffic": round(traffic) if traffic is not None else None,
-            "kernel": "trace_kernel", "bytes_per_ray": round(mean_b, 2),
-            "bytes_per_launch": round(bytes_per_launch), "launch_ms": round(float(trace_ms.mean()), 4),
+            "kernel": "beam_kernel + trace_kernel" if args.beam else "trace_kernel",
+            "bytes_per_ray": round(mean_b, 2),
+            "bytes_per_launch": round(bytes_per_launch), "launch_ms": round(float(pass_ms.mean()), 4),
         }
         if "valu_insts_per_launch" in prof:
             # VALU issue view: wave instructions per second over the issue peak
             # (1024 SIMDs x 2.4 GHz / 4 cycles per wave64 VALU instruction)
-            rate = float(prof["valu_insts_per_launch"]) / (trace_ms.mean() * 1e-3)
+            rate = float(prof["valu_insts_per_launch"]) / (trace_ms.mean() * 1e-3)  # trace kernel alone
             peak = 1024 * 2.4e9 / 4
             result["valu_issue"] = {"achieved": round(rate / 1e9, 2), "peak": round(peak / 1e9, 2),
                                     "unit": "G wave-instructions/s", "frac": round(rate / peak, 4)}

@@ -42,8 +42,9 @@ extern "C" {
 #define SVD_ERANGE (-5)    /* value outside the exact-integer range */
 #define SVD_ENOTFOUND (-6) /* chunk not resident */
 
-/* svd_trace_view flags */
-#define SVD_NO_CULL 1u     /* skip frustum culling (results are identical) */
+/* Trace flags (results are identical with any of them) */
+#define SVD_NO_CULL 1u     /* skip frustum culling */
+#define SVD_BEAM 2u        /* run the beam pass first (rays start at their tile's bound) */
 
 /* Message of the last failure on this thread (static storage, never NULL). */
 const char* svd_last_error(void);
@@ -209,7 +210,7 @@ int svd_camera_frame(const svd_camera* cam, svd_ray_frame* out);
 /* Trace one view: enqueue the chunk stage (LOD pick and frustum cull per
  * chunk) and the per-pixel trace on `stream`.
  *   out_dev  width*height svd_hit records (device, caller-owned).
- *   flags    SVD_NO_CULL or 0.
+ *   flags    SVD_NO_CULL, SVD_BEAM or 0.
  * Errors: SVD_EINVAL, SVD_ERANGE (camera), SVD_ENOTFOUND (some (chunk, LOD)
  * was never uploaded nor described), SVD_EDEVICE. */
 int svd_trace_view(svd_world* w, const svd_camera* cam, svd_hit* out_dev, uint32_t flags,
@@ -220,16 +221,28 @@ int svd_trace_view(svd_world* w, const svd_camera* cam, svd_hit* out_dev, uint32
 int svd_trace_frame(svd_world* w, const svd_ray_frame* frame, svd_hit* out_dev, uint32_t flags,
                     void* stream);
 
-/* The two halves of a traced view, for callers that time or schedule them
+/* The parts of a traced view, for callers that time or schedule them
  * separately.
  * svd_view_stage: the chunk stage (Section 3.5 chunk selection pass): per
  *   chunk, the LOD by camera distance (Eq. 1) and a conservative frustum
  *   cull of its tight box at that LOD, written to the world's view table.
- *   Errors as svd_trace_frame.
+ *   Errors as svd_trace_frame.  flags: SVD_NO_CULL, SVD_BEAM.
+ * svd_view_beam (optional): the beam pass (ESVO's beam optimisation, Section
+ *   2.2: a coarse distance pass that moves the rays' starting points; here
+ *   made exact, so records do not change): per 16x4-pixel tile, a
+ *   distance within which no ray of the tile can meet a cell it could hit,
+ *   parked in the tile's first record of out_dev.  The next svd_view_trace
+ *   into the same out_dev then starts each ray there instead of running the
+ *   pass itself.  Nothing is done unless the view was staged with SVD_BEAM.
  * svd_view_trace: the per-pixel trace (Section 3.5 ray marching and colour
  *   resolve) over the view table of the last svd_view_stage, which must have
- *   been given an identical frame (else SVD_EINVAL). */
+ *   been given an identical frame (else SVD_EINVAL); with SVD_BEAM staged,
+ *   runs the beam pass first unless svd_view_beam did.
+ * The beam pass is off by default: on MI355X it cuts the trace's
+ * instructions about 2x but hardly its time (the surface iterations it
+ * leaves are bound by dependent-load latency), and costs more than it saves. */
 int svd_view_stage(svd_world* w, const svd_ray_frame* frame, uint32_t flags, void* stream);
+int svd_view_beam(svd_world* w, const svd_ray_frame* frame, svd_hit* out_dev, void* stream);
 int svd_view_trace(svd_world* w, const svd_ray_frame* frame, svd_hit* out_dev, void* stream);
 
 /* Occupancy of the per-view persistent trace: the grid is blocks_per_cu x
@@ -351,7 +364,7 @@ int svd_server_set_chunk(svd_server* s, const uint32_t c[3], const svd_blob* b);
 /* Queue a request; returns at once.  out_dev: width*height records (device),
  * with no pending work of the caller's (the server's streams do not wait
  * for other streams) and untouched until the request is reported done.  flags:
- * SVD_NO_CULL or 0.  Camera errors as svd_camera_frame, synchronously.
+ * SVD_NO_CULL, SVD_BEAM or 0.  Camera errors as svd_camera_frame, synchronously.
  * Thread-safe. */
 int svd_server_submit(svd_server* s, const svd_camera* cam, svd_hit* out_dev, uint32_t flags, uint64_t tag);
 /* Up to `max` finished requests (oldest first) into out, their count in *n;

@@ -65,7 +65,8 @@ __host__ __device__ inline uint32_t stage_chunk(const StageParams& p, uint32_t c
     d2 += (unsigned __int128)(diff * diff);
   }
   uint32_t k = 0;
-  for (uint32_t j = 0; j + 1 < p.lod_count; j++) {
+  _Pragma("unroll") for (uint32_t j = 0; j < 3; j++) {
+    if (j + 1 >= p.lod_count) break;
     const unsigned __int128 t = (unsigned __int128)p.thr[j] << 16;
     if (d2 >= t * t) k++;
   }
@@ -81,7 +82,7 @@ __host__ __device__ inline uint32_t stage_chunk(const StageParams& p, uint32_t c
       hi[a] = ((__int128)(base + ((int64_t)(d.hi[a] + 1) << k)) << 16) - p.O[a];
     }
     bool culled = false;
-    for (int i = 0; i < 4; i++) {
+    _Pragma("unroll") for (int i = 0; i < 4; i++) {
       __int128 s = 0;
       _Pragma("unroll") for (int a = 0; a < 3; a++) s += (__int128)p.n[i][a] * (p.n[i][a] >= 0 ? hi[a] : lo[a]);
       if (s < 0) culled = true;
@@ -165,7 +166,7 @@ struct Ray {
 // traversal, hit resolve.  `stk` is this ray's node-word stack (levels 3..10,
 // element stride `ss`).
 __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, uint32_t py,
-                                             uint32_t* stk, uint32_t ss) {
+                                             uint32_t* stk, uint32_t ss, uint32_t start) {
   const int CL = (int)p.chunk_log2;
   int32_t D[3];
   Ray r;
@@ -190,9 +191,20 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
     const uint64_t l = (uint64_t)n * d0, q = (uint64_t)n0 * r.ad[a];
     if (l > q || (l == q && cl > c0)) { n0 = n; d0 = r.ad[a]; c0 = cl; }
   }
+  uint32_t status = kRunning;
+  // Start bound of the tile (beam pass): no cell the ray can hit lies within
+  // Chebyshev distance `start` voxels of the camera, and the ray is at that
+  // distance at t = start 2^16 / max|D_a|; begin there if that is later.
+  if (start == kBeamNone) {
+    status = kMiss;
+  } else if (start) {
+    const uint32_t m01 = r.ad[0] > r.ad[1] ? r.ad[0] : r.ad[1];
+    const uint32_t mad = m01 > r.ad[2] ? m01 : r.ad[2];
+    const uint32_t nb = start << 16;
+    if ((uint64_t)nb * d0 > (uint64_t)n0 * mad) { n0 = nb; d0 = mad; c0 = 0; }
+  }
   r.set_time(n0, d0, c0);
 
-  uint32_t status = kRunning;
   int32_t c[3];
   uint32_t E[3];  // exit-plane numerators of cell c at level lev
   _Pragma("unroll") for (int a = 0; a < 3; a++) {
@@ -387,10 +399,11 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceParams p) {
       }
       break;
     }
-    const uint32_t px = (t % p.tiles_x) * tw + lane % tw;
-    const uint32_t py = (t / p.tiles_x) * th + lane / tw;
-    if (px < p.W && py < p.H)
-      reinterpret_cast<uint4*>(p.out)[(size_t)py * p.W + px] = trace_pixel(p, px, py, &stk[0][tid], kBlock);
+    const uint32_t x0 = (t % p.tiles_x) * tw, y0 = (t / p.tiles_x) * th;
+    const uint32_t px = x0 + lane % tw, py = y0 + lane / tw;
+    uint4* out = reinterpret_cast<uint4*>(p.out);
+    const uint32_t start = p.beam ? out[(size_t)y0 * p.W + x0].x : 0u;  // read before the tile is written
+    if (px < p.W && py < p.H) out[(size_t)py * p.W + px] = trace_pixel(p, px, py, &stk[0][tid], kBlock, start);
   }
 }
 
@@ -406,6 +419,189 @@ int launch_trace(const TraceParams& p, uint32_t blocks, void* stream) {
   hipLaunchKernelGGL(trace_kernel, dim3(blocks), dim3(kBlock), 0, (hipStream_t)stream, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return svd_fail(SVD_EDEVICE, "trace launch: %s", hipGetErrorString(e));
+  return SVD_OK;
+}
+
+// ------------------------------------------------------------- beam pass
+// ESVO's beam optimisation (Section 2.2: a coarse pass that moves the rays'
+// starting points; Section 4.1 compares against it), made exact.  One lane
+// per wave tile computes a lower bound d on the Chebyshev distance from the
+// camera to every cell that a ray of the tile could hit: the minimum over
+// the cubes that may hold such a cell (chunk tight boxes, then DAG children
+// down to 2^3 sub-blocks of the picked LOD, or a whole chunk whose LOD is not
+// loaded) that reach the cone of the tile's corner rays.  Every pixel ray of
+// the tile lies in that cone (directions are affine in the pixel), and a
+// ray point at time t < d 2^16 / max|D_a| is nearer than d in the Chebyshev
+// norm, so it lies outside every such closed cube: the ray visits only empty
+// cells before that time, and starting its walk there (same exact instant
+// arithmetic as the world entry) changes no record.
+//
+// The cone test is conservative in FP64: its side planes n_i = C_i x C_(i+1)
+// are exact in i64 (|C| < 2^31) and rounded once to FP64 (error <= 2^10 per
+// component); box offsets are exact (< 2^34); the three products and two
+// sums then err by less than 2^47, so a cube is dropped only when its
+// farthest corner along n_i scores below -2^49.
+struct BeamCone {
+  double n[4][3];
+  uint32_t mm;  // near-first octant order: bit a set when the tile looks down axis a
+};
+
+__host__ __device__ inline bool beam_cone(const BeamParams& p, uint32_t x0, uint32_t y0, uint32_t x1, uint32_t y1,
+                                          BeamCone& q) {
+  int64_t C[4][3];
+  const uint32_t px[4] = {x0, x1, x1, x0}, py[4] = {y0, y0, y1, y1};
+  _Pragma("unroll") for (int i = 0; i < 4; i++)
+    _Pragma("unroll") for (int a = 0; a < 3; a++) C[i][a] = p.A[a] + (int64_t)px[i] * p.BX[a] + (int64_t)py[i] * p.BY[a];
+  q.mm = 0;
+  _Pragma("unroll") for (int a = 0; a < 3; a++)
+    if (C[0][a] + C[2][a] < 0) q.mm |= 1u << a;
+  _Pragma("unroll") for (int i = 0; i < 4; i++) {
+    const int64_t* u = C[i];
+    const int64_t* v = C[(i + 1) & 3];
+    const int64_t m[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+    __int128 s0 = 0, s1 = 0;
+    _Pragma("unroll") for (int a = 0; a < 3; a++) {
+      s0 += (__int128)m[a] * C[(i + 2) & 3][a];
+      s1 += (__int128)m[a] * C[(i + 3) & 3][a];
+    }
+    double sg;
+    if (s0 >= 0 && s1 >= 0 && (s0 > 0 || s1 > 0)) sg = 1.0;
+    else if (s0 <= 0 && s1 <= 0 && (s0 < 0 || s1 < 0)) sg = -1.0;
+    else return false;  // degenerate cone (a one-pixel row or column)
+    _Pragma("unroll") for (int a = 0; a < 3; a++) q.n[i][a] = sg * (double)m[a];
+  }
+  return true;
+}
+
+// Closed cube [lo, lo + size] (voxels) entirely outside the cone?
+__host__ __device__ __forceinline__ bool beam_outside(const BeamCone& q, const int64_t O[3], const int64_t lo[3],
+                                                      int64_t size) {
+  bool out = false;
+  _Pragma("unroll") for (int i = 0; i < 4; i++) {
+    double sdot = 0.0;
+    _Pragma("unroll") for (int a = 0; a < 3; a++) {
+      const int64_t x = ((q.n[i][a] >= 0.0 ? lo[a] + size : lo[a]) << 16) - O[a];
+      sdot = sdot + q.n[i][a] * (double)x;
+    }
+    out |= sdot < -0x1p49;
+  }
+  return out;
+}
+
+// Chebyshev distance from O to the closed box [lo, hi] (voxels), in whole
+// voxels rounded down, at most 65535.
+__host__ __device__ __forceinline__ uint32_t beam_dist(const int64_t O[3], const int64_t lo[3], const int64_t hi[3]) {
+  int64_t d = 0;
+  _Pragma("unroll") for (int a = 0; a < 3; a++) {
+    const int64_t l = lo[a] << 16, h = hi[a] << 16;
+    const int64_t e = O[a] < l ? l - O[a] : (O[a] > h ? O[a] - h : 0);
+    d = e > d ? e : d;
+  }
+  d >>= 16;
+  return (uint32_t)(d < 65535 ? d : 65535);
+}
+
+// Start bound of the tile with pixel corners (x0, y0)..(x1, y1).  `stk` holds
+// the DFS path (two words per node level, element stride `ss`).
+__host__ __device__ inline uint32_t beam_tile(const BeamParams& p, uint32_t x0, uint32_t y0, uint32_t x1, uint32_t y1,
+                                              uint32_t* stk, uint32_t ss) {
+  BeamCone q;
+  if (!beam_cone(p, x0, y0, x1, y1, q)) return 0u;
+  const int CL = (int)p.chunk_log2;
+  const int64_t S = (int64_t)1 << CL;
+  int64_t c0[3], rmin = 0, rmax = 0;
+  _Pragma("unroll") for (int a = 0; a < 3; a++) {
+    c0[a] = (p.O[a] >> 16) >> CL;  // chunk of the camera (floor), maybe outside the grid
+    const int64_t g = (int64_t)p.grid[a];
+    const int64_t in = c0[a] < 0 ? -c0[a] : (c0[a] >= g ? c0[a] - g + 1 : 0);
+    const int64_t out = c0[a] < 0 ? g - 1 - c0[a] : (c0[a] >= g ? c0[a] : (c0[a] > g - 1 - c0[a] ? c0[a] : g - 1 - c0[a]));
+    rmin = in > rmin ? in : rmin;
+    rmax = out > rmax ? out : rmax;
+  }
+  uint32_t best = kBeamNone;
+  for (int64_t r = rmin; r <= rmax; r++) {
+    // every chunk of ring r is at least (r - 1) chunks away on some axis
+    if (r >= 1 && best != kBeamNone && (uint64_t)((r - 1) * S) >= best) break;
+    const int64_t zl = c0[2] - r < 0 ? 0 : c0[2] - r, zh = c0[2] + r >= p.grid[2] ? p.grid[2] - 1 : c0[2] + r;
+    const int64_t yl = c0[1] - r < 0 ? 0 : c0[1] - r, yh = c0[1] + r >= p.grid[1] ? p.grid[1] - 1 : c0[1] + r;
+    for (int64_t z = zl; z <= zh; z++) {
+      for (int64_t y = yl; y <= yh; y++) {
+        const bool face = z == c0[2] - r || z == c0[2] + r || y == c0[1] - r || y == c0[1] + r;
+        const int64_t step = face || r == 0 ? 1 : 2 * r;
+        for (int64_t x = c0[0] - r; x <= c0[0] + r; x += step) {
+          if (x < 0 || x >= (int64_t)p.grid[0]) continue;
+          const uint32_t ci = (uint32_t)(x + p.grid[0] * (y + p.grid[1] * z));
+          const uint32_t v = p.view[ci];
+          if (v & (kViewCulled | kViewEmpty)) continue;
+          const int k = (int)(v & kViewLodMask);
+          const int64_t base[3] = {x * S, y * S, z * S};
+          if (v & kViewMissing) {  // rays must reach it to report it
+            const int64_t hi[3] = {base[0] + S, base[1] + S, base[2] + S};
+            const uint32_t d = beam_dist(p.O, base, hi);
+            if (d < best && !beam_outside(q, p.O, base, S)) best = d;
+            continue;
+          }
+          const DevDag* dag = &p.desc[(size_t)ci * 4 + k];
+          // depth-first over the DAG, nearest octants first, cut by the bound so far
+          const gptr32 nodes = (gptr32)dag->nodes;
+          int L = CL;
+          uint32_t wd = dag->root, it = 0;
+          int64_t org[3] = {base[0], base[1], base[2]};
+          for (;;) {
+            if (it == 8) {
+              if (L == CL) break;
+              L++;
+              wd = stk[(2 * (L - 3)) * ss];
+              it = stk[(2 * (L - 3) + 1) * ss];
+              _Pragma("unroll") for (int a = 0; a < 3; a++) org[a] = base[a] + ((org[a] - base[a]) & ~(((int64_t)1 << L) - 1));
+              continue;
+            }
+            const uint32_t o = it ^ q.mm;
+            it++;
+            if (!((wd >> (kPtrBits + o)) & 1u)) continue;
+            const int64_t half = (int64_t)1 << (L - 1);
+            const int64_t lo[3] = {org[0] + ((o & 1) ? half : 0), org[1] + ((o & 2) ? half : 0),
+                                   org[2] + ((o & 4) ? half : 0)};
+            const int64_t hi[3] = {lo[0] + half, lo[1] + half, lo[2] + half};
+            const uint32_t d = beam_dist(p.O, lo, hi);
+            if (d >= best || beam_outside(q, p.O, lo, half)) continue;
+            if (L - 1 == k + 1) {  // a 2^3 sub-block of a leaf: as fine as the bound goes
+              best = d;
+              continue;
+            }
+            const uint32_t cw = nodes[(wd & kPtrMask) + __builtin_popcount((wd >> kPtrBits) & ((1u << o) - 1u))];
+            stk[(2 * (L - 3)) * ss] = wd;
+            stk[(2 * (L - 3) + 1) * ss] = it;
+            L--;
+            wd = cw;
+            it = 0;
+            _Pragma("unroll") for (int a = 0; a < 3; a++) org[a] = lo[a];
+          }
+        }
+      }
+    }
+  }
+  return best;
+}
+
+constexpr int kBeamBlock = 64;
+
+__global__ __launch_bounds__(kBeamBlock) void beam_kernel(BeamParams p) {
+  __shared__ uint32_t stk[2 * kStackLevels][kBeamBlock];
+  const uint32_t t = blockIdx.x * kBeamBlock + threadIdx.x;
+  if (t >= p.total_tiles) return;
+  const uint32_t th = 64 / p.tile_w;
+  const uint32_t x0 = (t % p.tiles_x) * p.tile_w, y0 = (t / p.tiles_x) * th;
+  const uint32_t x1 = min(x0 + p.tile_w, p.W) - 1, y1 = min(y0 + th, p.H) - 1;
+  const uint32_t d = beam_tile(p, x0, y0, x1, y1, &stk[0][threadIdx.x], kBeamBlock);
+  reinterpret_cast<uint32_t*>(p.out)[((size_t)y0 * p.W + x0) * 4] = d;
+}
+
+int launch_beam(const BeamParams& p, void* stream) {
+  const uint32_t blocks = (p.total_tiles + kBeamBlock - 1) / kBeamBlock;
+  hipLaunchKernelGGL(beam_kernel, dim3(blocks), dim3(kBeamBlock), 0, (hipStream_t)stream, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return svd_fail(SVD_EDEVICE, "beam launch: %s", hipGetErrorString(e));
   return SVD_OK;
 }
 
@@ -444,7 +640,7 @@ __global__ __launch_bounds__(kBlock) void batch_trace_kernel(BatchParams p) {
   __shared__ uint32_t stk[kStackLevels][kBlock];
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t total = p.hdr->total_tiles, nviews = p.hdr->nviews;
-  const uint32_t claim = p.hdr->claim, tw = p.hdr->tile_w, th = 64 / tw;
+  const uint32_t claim = p.hdr->claim, tw = p.hdr->tile_w, th = 64 / tw, beam = p.hdr->beam;
   for (;;) {
     // one queue access per wave: lane 0 claims, the wave shares the index
     uint32_t t0 = 0;
@@ -460,8 +656,10 @@ __global__ __launch_bounds__(kBlock) void batch_trace_kernel(BatchParams p) {
       }
       const BatchView& bv = p.views[lo];
       const uint32_t lt = t - bv.tile_base;
-      const uint32_t px = (lt % bv.tiles_x) * tw + lane % tw;
-      const uint32_t py = (lt / bv.tiles_x) * th + lane / tw;
+      const uint32_t x0 = (lt % bv.tiles_x) * tw, y0 = (lt / bv.tiles_x) * th;
+      const uint32_t px = x0 + lane % tw, py = y0 + lane / tw;
+      uint4* out = reinterpret_cast<uint4*>(bv.out);
+      const uint32_t start = beam ? out[(size_t)y0 * bv.W + x0].x : 0u;  // read before the tile is written
       if (px >= bv.W || py >= bv.H) continue;
       TraceParams tp;
       _Pragma("unroll") for (int a = 0; a < 3; a++) {
@@ -474,7 +672,7 @@ __global__ __launch_bounds__(kBlock) void batch_trace_kernel(BatchParams p) {
       tp.chunk_log2 = p.chunk_log2;
       tp.view = p.view_tables + (size_t)lo * p.nchunks;
       tp.desc = p.desc;
-      reinterpret_cast<uint4*>(bv.out)[(size_t)py * bv.W + px] = trace_pixel(tp, px, py, &stk[0][tid], kBlock);
+      out[(size_t)py * bv.W + px] = trace_pixel(tp, px, py, &stk[0][tid], kBlock, start);
     }
   }
 }
@@ -487,10 +685,48 @@ int batch_trace_occupancy(uint32_t* blocks_per_cu) {
   return SVD_OK;
 }
 
+// Beam pass over every tile of the batch (grid-stride: the grid is fixed when
+// the graph is captured).
+__global__ __launch_bounds__(kBeamBlock) void batch_beam_kernel(BatchParams p) {
+  __shared__ uint32_t stk[2 * kStackLevels][kBeamBlock];
+  if (!p.hdr->beam) return;
+  const uint32_t total = p.hdr->total_tiles, nviews = p.hdr->nviews;
+  const uint32_t tw = p.hdr->tile_w, th = 64 / tw;
+  for (uint32_t t = blockIdx.x * kBeamBlock + threadIdx.x; t < total; t += gridDim.x * kBeamBlock) {
+    uint32_t lo = 0, hi = nviews;  // view holding global tile t
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (p.views[mid].tile_base <= t) lo = mid; else hi = mid;
+    }
+    const BatchView& bv = p.views[lo];
+    BeamParams bp;
+    _Pragma("unroll") for (int a = 0; a < 3; a++) {
+      bp.O[a] = bv.O[a];
+      bp.A[a] = bv.A[a];
+      bp.BX[a] = bv.BX[a];
+      bp.BY[a] = bv.BY[a];
+      bp.grid[a] = p.grid[a];
+    }
+    bp.W = bv.W;
+    bp.H = bv.H;
+    bp.tiles_x = bv.tiles_x;
+    bp.tile_w = tw;
+    bp.chunk_log2 = p.chunk_log2;
+    bp.view = p.view_tables + (size_t)lo * p.nchunks;
+    bp.desc = p.desc;
+    const uint32_t lt = t - bv.tile_base;
+    const uint32_t x0 = (lt % bv.tiles_x) * tw, y0 = (lt / bv.tiles_x) * th;
+    const uint32_t x1 = min(x0 + tw, bv.W) - 1, y1 = min(y0 + th, bv.H) - 1;
+    const uint32_t d = beam_tile(bp, x0, y0, x1, y1, &stk[0][threadIdx.x], kBeamBlock);
+    reinterpret_cast<uint32_t*>(bv.out)[((size_t)y0 * bv.W + x0) * 4] = d;
+  }
+}
+
 int launch_batch(const BatchParams& p, uint32_t trace_blocks, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, p.hdr);
   hipLaunchKernelGGL(batch_stage_kernel, dim3((p.nchunks + 63) / 64, p.max_views), dim3(64), 0, s, p);
+  hipLaunchKernelGGL(batch_beam_kernel, dim3(trace_blocks), dim3(kBeamBlock), 0, s, p);
   hipLaunchKernelGGL(batch_trace_kernel, dim3(trace_blocks), dim3(kBlock), 0, s, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return svd_fail(SVD_EDEVICE, "batch launch: %s", hipGetErrorString(e));

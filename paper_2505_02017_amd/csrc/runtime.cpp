@@ -412,7 +412,7 @@ StageParams world_stage_params(const svd_world* w, const svd_ray_frame* f, bool 
 
 extern "C" int svd_view_stage(svd_world* w, const svd_ray_frame* f, uint32_t flags, void* stream) {
   if (!w || !f) return svd_fail(SVD_EINVAL, "svd_view_stage: null argument");
-  if (flags & ~SVD_NO_CULL) return svd_fail(SVD_EINVAL, "stage: unknown flags");
+  if (flags & ~(SVD_NO_CULL | SVD_BEAM)) return svd_fail(SVD_EINVAL, "stage: unknown flags");
   int rc = check_frame(f);
   if (rc) return rc;
   if (w->absent) return svd_fail(SVD_ENOTFOUND, "stage: %u (chunk, LOD) slots were never uploaded", w->absent);
@@ -422,7 +422,37 @@ extern "C" int svd_view_stage(svd_world* w, const svd_ray_frame* f, uint32_t fla
   if (rc) return rc;
   w->staged = *f;
   w->has_staged = true;
+  w->staged_beam = (flags & SVD_BEAM) != 0;
+  w->beamed = nullptr;
   return SVD_OK;
+}
+
+extern "C" int svd_view_beam(svd_world* w, const svd_ray_frame* f, svd_hit* out_dev, void* stream) {
+  if (!w || !f || !out_dev) return svd_fail(SVD_EINVAL, "svd_view_beam: null argument");
+  if (!w->has_staged || !same_frame(w->staged, *f))
+    return svd_fail(SVD_EINVAL, "beam: the frame was not staged by the last svd_view_stage");
+  if (w->absent) return svd_fail(SVD_ENOTFOUND, "beam: %u (chunk, LOD) slots were never uploaded", w->absent);
+  if (!w->staged_beam) return SVD_OK;
+  BeamParams bp;
+  memset(&bp, 0, sizeof(bp));
+  memcpy(bp.O, f->O, sizeof(bp.O));
+  memcpy(bp.A, f->A, sizeof(bp.A));
+  memcpy(bp.BX, f->BX, sizeof(bp.BX));
+  memcpy(bp.BY, f->BY, sizeof(bp.BY));
+  bp.W = f->width;
+  bp.H = f->height;
+  bp.tiles_x = (f->width + kViewTileW - 1) / kViewTileW;
+  const uint64_t th = 64 / kViewTileW;
+  bp.total_tiles = (uint32_t)((uint64_t)bp.tiles_x * ((f->height + th - 1) / th));
+  bp.tile_w = kViewTileW;
+  memcpy(bp.grid, w->desc.grid, sizeof(bp.grid));
+  bp.chunk_log2 = w->desc.chunk_log2;
+  bp.view = w->d_view;
+  bp.desc = w->d_desc;
+  bp.out = out_dev;
+  const int rc = launch_beam(bp, stream);
+  if (rc == SVD_OK) w->beamed = out_dev;
+  return rc;
 }
 
 extern "C" int svd_view_trace(svd_world* w, const svd_ray_frame* f, svd_hit* out_dev, void* stream) {
@@ -448,6 +478,12 @@ extern "C" int svd_view_trace(svd_world* w, const svd_ray_frame* f, svd_hit* out
   tp.view = w->d_view;
   tp.desc = w->d_desc;
   tp.out = out_dev;
+  tp.beam = w->staged_beam;
+  if (tp.beam && w->beamed != out_dev) {  // per-tile start bounds, parked in each tile's first record
+    const int rc = svd_view_beam(w, f, out_dev, stream);
+    if (rc) return rc;
+  }
+  w->beamed = nullptr;
   // a persistent grid, but no more waves (4 per block) than there are tiles
   const uint32_t blocks = std::min<uint64_t>((uint64_t)w->per_cu * w->cus, (tp.total_tiles + 3) / 4);
   return launch_trace(tp, blocks, stream);
@@ -623,7 +659,7 @@ extern "C" int svd_batch_get_tiling(const svd_batch* b, uint32_t* tile_w, uint32
 int batch_enqueue(svd_batch* b, const svd_ray_frame* frames, svd_hit* const* outs, uint32_t n, uint32_t flags,
                   hipStream_t s) {
   if (n == 0 || n > b->max_views) return svd_fail(SVD_EINVAL, "batch: %u views, 1..%u allowed", n, b->max_views);
-  if (flags & ~SVD_NO_CULL) return svd_fail(SVD_EINVAL, "batch: unknown flags");
+  if (flags & ~(SVD_NO_CULL | SVD_BEAM)) return svd_fail(SVD_EINVAL, "batch: unknown flags");
   svd_world* w = b->w;
   if (w->absent) return svd_fail(SVD_ENOTFOUND, "batch: %u (chunk, LOD) slots were never uploaded", w->absent);
   const uint32_t tw = b->tile_w, th = 64 / tw;
@@ -648,6 +684,7 @@ int batch_enqueue(svd_batch* b, const svd_ray_frame* frames, svd_hit* const* out
   h->total_tiles = (uint32_t)tiles;
   h->tile_w = tw;
   h->claim = b->claim;
+  h->beam = (flags & SVD_BEAM) != 0;
   uint32_t tbase = 0;
   for (uint32_t v = 0; v < n; v++) {
     const svd_ray_frame& f = frames[v];

@@ -396,7 +396,7 @@ extern "C" int svd_server_set_chunk(svd_server* s, const uint32_t c[3], const sv
 extern "C" int svd_server_submit(svd_server* s, const svd_camera* cam, svd_hit* out_dev, uint32_t flags,
                                  uint64_t tag) {
   if (!s || !cam || !out_dev) return svd_fail(SVD_EINVAL, "svd_server_submit: null argument");
-  if (flags & ~SVD_NO_CULL) return svd_fail(SVD_EINVAL, "serve: unknown flags");
+  if (flags & ~(SVD_NO_CULL | SVD_BEAM)) return svd_fail(SVD_EINVAL, "serve: unknown flags");
   Request r;
   int rc = svd_camera_frame(cam, &r.frame);
   if (rc) return rc;

@@ -79,8 +79,27 @@ struct TraceParams {
   const uint32_t* view;   // per-chunk view entry
   const DevDag* desc;     // [chunk * 4 + lod]
   svd_hit* out;
+  uint32_t beam;          // 1: each tile's first record holds its start bound
 };
 constexpr uint32_t kViewTileW = 16;  // per-view wave tile: 16 x 4 pixels
+
+// Start bound of a tile, written by the beam pass into the first word of the
+// tile's first record (the trace reads it before writing the tile): whole
+// voxels of Chebyshev distance from the camera within which no ray of the
+// tile meets a cell it could hit (or a chunk whose LOD is not loaded).
+// kBeamNone: no ray of the tile meets one at all.
+constexpr uint32_t kBeamNone = 0xFFFFFFFFu;
+
+struct BeamParams {
+  int64_t O[3], A[3], BX[3], BY[3];
+  uint32_t W, H;
+  uint32_t tiles_x, total_tiles, tile_w;
+  uint32_t grid[3];
+  uint32_t chunk_log2;
+  const uint32_t* view;
+  const DevDag* desc;
+  svd_hit* out;
+};
 
 struct StageParams {
   int64_t O[3];
@@ -115,7 +134,8 @@ struct alignas(64) BatchHeader {
   uint32_t next_tile;     // work-queue head (reset by a kernel, not a memset)
   uint32_t tile_w;        // tile width in pixels (tile = tile_w x 64/tile_w)
   uint32_t claim;         // tiles a wave takes per queue access
-  uint32_t pad[11];
+  uint32_t beam;          // 1: run the beam pass (tile start bounds)
+  uint32_t pad[10];
 };
 static_assert(sizeof(BatchHeader) == 64, "BatchHeader must stay 64 bytes");
 
@@ -140,6 +160,7 @@ int check_frame(const svd_ray_frame* f);
 int launch_chunk_stage(const StageParams& p, void* stream);
 uint32_t host_stage_chunk(const StageParams& p, uint32_t ci);  // the stage's decision, on the host
 int launch_trace(const TraceParams& p, uint32_t blocks, void* stream);
+int launch_beam(const BeamParams& p, void* stream);
 int trace_occupancy(uint32_t* blocks_per_cu);
 int launch_set_desc(DevDag* dst, const DevDag* src4, uint32_t n, void* stream);
 // batched views: queue reset, per-(view, chunk) stage, persistent trace
@@ -196,6 +217,8 @@ struct svd_world {
   size_t used = 0;
   svd_ray_frame staged;  // frame of the last chunk stage (its view table)
   bool has_staged = false;
+  bool staged_beam = false;  // the trace of the staged view runs the beam pass
+  const svd_hit* beamed = nullptr;  // output that already holds the staged view's tile bounds
 
   bool alloc(size_t bytes, size_t* off) {
     bytes = (bytes + 255) / 256 * 256;

@@ -23,6 +23,7 @@ SVD_EFORMAT = -4
 SVD_ERANGE = -5
 SVD_ENOTFOUND = -6
 SVD_NO_CULL = 1
+SVD_BEAM = 2
 FAULT_CHUNK = 0xFFFFFFFE  # written by the trace if its iteration guard fires
 CHUNK_NOT_LOADED = 0xFFFFFFFD  # a ray reached a chunk whose picked LOD is only described
 
@@ -34,7 +35,7 @@ EXPORTS = [
     "svd_blob_free", "svd_free", "svd_blob_stats_get", "svd_blob_canonical",
     "svd_world_create", "svd_world_destroy", "svd_world_pool_used", "svd_chunk_upload",
     "svd_chunk_evict", "svd_chunk_upload_lods", "svd_chunk_evict_lods", "svd_camera_frame", "svd_trace_view", "svd_trace_frame",
-    "svd_view_stage", "svd_view_trace", "svd_view_table",
+    "svd_view_stage", "svd_view_beam", "svd_view_trace", "svd_view_table",
     "svd_world_set_occupancy", "svd_world_get_occupancy",
     "svd_batch_create", "svd_batch_destroy", "svd_batch_trace", "svd_batch_trace_frames",
     "svd_batch_set_tiling", "svd_batch_set_occupancy", "svd_batch_get_tiling", "svd_batch_tune",
@@ -127,6 +128,7 @@ def lib() -> ctypes.CDLL:
         L.svd_view_table.argtypes = [vp, ctypes.POINTER(u32), u32, vp]
         L.svd_view_stage.argtypes = [vp, ctypes.POINTER(svd_ray_frame), u32, vp]
         L.svd_view_trace.argtypes = [vp, ctypes.POINTER(svd_ray_frame), vp, vp]
+        L.svd_view_beam.argtypes = [vp, ctypes.POINTER(svd_ray_frame), vp, vp]
         L.svd_world_set_occupancy.argtypes = [vp, u32]
         L.svd_world_get_occupancy.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32)]
         u64 = ctypes.c_uint64
@@ -376,6 +378,11 @@ def svd_trace_frame(w: World, frame: svd_ray_frame, out, flags: int = 0, stream=
 
 def svd_view_stage(w: World, frame: svd_ray_frame, flags: int = 0, stream=None):
     _check(lib().svd_view_stage(w.ptr, ctypes.byref(frame), flags, _stream_ptr(stream)))
+
+
+def svd_view_beam(w: World, frame: svd_ray_frame, out, stream=None):
+    _check(lib().svd_view_beam(w.ptr, ctypes.byref(frame), _out_ptr(out, frame.width * frame.height),
+                               _stream_ptr(stream)))
 
 
 def svd_view_trace(w: World, frame: svd_ray_frame, out, stream=None):

@@ -71,6 +71,10 @@ def test_batch_equals_per_view_all_tilings(env, world):
             svdag.svd_batch_trace(b, cams, out)
             torch.cuda.synchronize()
             assert np.array_equal(out.cpu().numpy(), ref), (tw, claim)
+    out_nb = torch.full_like(out, -1)
+    svdag.svd_batch_trace(b, cams, out_nb, svdag.SVD_BEAM)
+    torch.cuda.synchronize()
+    assert np.array_equal(out_nb.cpu().numpy(), ref), "batch with the beam pass"
     # and the batch agrees with the oracle view by view
     raw, off = out.cpu().numpy(), 0
     for v, c in enumerate(cams):

@@ -89,8 +89,10 @@ def test_tiny_worlds_adversarial_frames(env, cfg):
     for i, (O, A, BX, BY, W, H) in enumerate(_frames(rng, ext, 40)):
         fr = svdag.make_frame(O, A, BX, BY, W, H)
         raw = trace_gpu(svdag, torch, w, fr)
-        lods = ow.lod_pick(np.array(O, np.int64), thr)
         vt = svdag.svd_view_table(w)
+        raw_nb = trace_gpu(svdag, torch, w, fr, flags=svdag.SVD_BEAM)
+        assert np.array_equal(raw, raw_nb), f"frame {i}: the beam pass changed a record"
+        lods = ow.lod_pick(np.array(O, np.int64), thr)
         assert np.array_equal(vt & 3, lods), f"frame {i}: LOD pick differs"
         ref = ow.trace_frame(lods, _oracle_frame(fr), mode=1, threads=NT)
         hits += compare(svdag, raw, ref, label=f"{cfg} frame {i}")
@@ -135,6 +137,8 @@ def test_terrain_lods_full_frames_cull_invariant(env, terrain):
         vt = svdag.svd_view_table(w)
         raw_nc = trace_gpu(svdag, torch, w, svdag.to_camera(cam), flags=svdag.SVD_NO_CULL)
         assert np.array_equal(raw, raw_nc), f"view {v}: culling changed the image"
+        raw_nb = trace_gpu(svdag, torch, w, svdag.to_camera(cam), flags=svdag.SVD_NO_CULL | svdag.SVD_BEAM)
+        assert np.array_equal(raw, raw_nb), f"view {v}: the beam pass changed the image"
         culled += int(np.count_nonzero(vt & 4))
         fr = oracle.camera_frame(cam)
         lods = ow.lod_pick(fr.O, thr)
