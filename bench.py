@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--serve-views", type=int, default=64, help="requests per batched launch")
     ap.add_argument("--serve-inflight", type=int, default=2, help="launches in flight")
     ap.add_argument("--serve-max-rays", type=int, default=8 << 20, help="rays per batched launch")
+    ap.add_argument("--serve-streaming-factor", type=float, default=1.5,
+                    help="streaming factor of the prefetching runs (0 = skip them)")
     ap.add_argument("--serve-speed", type=float, default=600.0,
                     help="walker speed, voxels/s (fast enough that the walkers' chunk sets outgrow the pool)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -416,12 +418,12 @@ def bench_served(args, sw, blobs, lod_count, thr, full_world, svdag, torch):
     old_switch = sys.getswitchinterval()
     sys.setswitchinterval(0.0005)
 
-    def run(mode, schedule, backlog):
+    def run(mode, schedule, backlog, sf=0.0):
         pool = torch.empty(svdag.table_bytes(sw.grid) + inflight * svdag.batch_bytes(nch, views) + budget,
                            dtype=torch.uint8, device="cuda")
         w = svdag.svd_world_create(desc, pool)
         s = svdag.svd_server_create(w, mode=mode, max_views=views, inflight=inflight,
-                                    max_rays=args.serve_max_rays)
+                                    max_rays=args.serve_max_rays, streaming_factor=sf)
         for ci, b in blobs.items():
             svdag.svd_server_set_chunk(s, coords[ci], b)
         torch.cuda.synchronize()
@@ -473,7 +475,8 @@ def bench_served(args, sw, blobs, lod_count, thr, full_world, svdag, torch):
              "p99_ms": round(float(np.percentile(lat[warm], 99)), 3),
              "mean_requests_per_launch": round(float(bv.mean()), 2), "launches": st["launches"],
              "uploads": st["uploads"], "upload_mib": round(st["upload_bytes"] / 2**20, 1),
-             "evictions": st["evictions"], "memory_waits": st["memory_waits"]}
+             "evictions": st["evictions"], "memory_waits": st["memory_waits"],
+             "prefetches": st["prefetches"], "prefetch_mib": round(st["prefetch_bytes"] / 2**20, 1)}
         # the last requests' records are still in the output ring: each equals its view traced alone
         ok = True
         for i in range(max(0, n - 8), n):
@@ -489,6 +492,7 @@ def bench_served(args, sw, blobs, lod_count, thr, full_world, svdag, torch):
            "pool_fraction": args.serve_pool_frac, "walkers": 8, "walker_speed": args.serve_speed,
            "resolutions": "uniform over 320x180, 640x360, 1280x720, 1920x1080",
            "batched_launch": {"max_requests": views, "max_rays": args.serve_max_rays, "inflight": inflight},
+           "prefetch_streaming_factor": args.serve_streaming_factor,
            "latency": "scheduled arrival to completion; requests arriving in the first second "
                       "(cold pool) are served but not in the percentiles"}
     modes = (("batched", svdag.SVD_SERVE_BATCHED), ("plain", svdag.SVD_SERVE_PLAIN))
@@ -497,9 +501,13 @@ def bench_served(args, sw, blobs, lod_count, thr, full_world, svdag, torch):
         for name, mode in modes:
             log(f"serving {len(sched)} requests at {rate:g}/s, {name}")
             res[f"{name}_{rate:g}rps"] = run(mode, sched, False)
+        if args.serve_streaming_factor > 0:
+            log(f"serving {len(sched)} requests at {rate:g}/s, batched with prefetch")
+            res[f"batched_prefetch_{rate:g}rps"] = run(svdag.SVD_SERVE_BATCHED, sched, False,
+                                                       args.serve_streaming_factor)
     sched = sw.walk_requests(8, 400.0, args.serve_backlog / 400.0 + 1.0, seed=99,
                              speed=args.serve_speed)[:args.serve_backlog]
-    for name, mode in modes:
+    for name, mode in (modes if args.serve_backlog > 0 else ()):
         log(f"serving {len(sched)} requests saturated, {name}")
         res[f"{name}_saturated"] = run(mode, sched, True)
     sys.setswitchinterval(old_switch)

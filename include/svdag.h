@@ -321,7 +321,19 @@ int svd_batch_tune(svd_batch* b, const svd_camera* cams, uint32_t n, svd_hit* ou
  *     slot frees (continuous batching);
  *   - SVD_SERVE_PLAIN traces each request with its own stage + trace launch
  *     pair, all on one stream, up to `inflight` queued (the per-request
- *     comparison).
+ *     comparison);
+ *   - with streaming_factor f > 0, the streaming policy of Section 3.4 runs
+ *     whenever a request's camera enters a chunk not among the last 8 seen:
+ *     an implicit octree over the chunk grid is walked from the root, a node
+ *     (a cube of 2^n chunks) being split while its LOD error (Eq. 1: the
+ *     distance at which its LOD gives way to a finer one, times max(f, 1),
+ *     minus its distance from the camera) is positive; the chunks of the
+ *     nodes where it stops are wanted at the LOD Eq. 1 picks with every
+ *     threshold stretched by f, and at the LOD it picks now.  Wanted slots
+ *     are uploaded, coarse LODs first and nearer first, into free pool space
+ *     while no request waits (1/8 of the pool stays free for demand), and
+ *     eviction takes unwanted slots before wanted ones.  Records never
+ *     depend on it.
  * Each request's records equal those of svd_trace_view of the same camera
  * on a world with every chunk resident.
  * ------------------------------------------------------------------------ */
@@ -337,6 +349,8 @@ typedef struct {
   uint32_t tile_w, claim;  /* batched: tiling (0 = the batch default) */
   uint32_t blocks_per_cu;  /* batched: persistent grid (0 = the batch default) */
   uint64_t max_rays;       /* batched: rays per launch (a larger request goes alone) */
+  float streaming_factor;  /* > 0: prefetch by the streaming policy (below); 0: demand only */
+  uint32_t reserved;       /* 0 */
 } svd_server_desc;
 
 typedef struct {
@@ -352,6 +366,7 @@ typedef struct {
   uint64_t uploads, upload_bytes, evictions, evict_bytes;
   uint64_t memory_waits;   /* requests that waited for in-flight work to release memory */
   uint64_t pool_used;      /* pool bytes holding chunk LODs */
+  uint64_t prefetches, prefetch_bytes;  /* uploads made by the streaming policy */
 } svd_server_stats;
 
 /* Batched mode takes inflight x svd_batch_create(w, max_views) pool space.

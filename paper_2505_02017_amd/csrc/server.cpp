@@ -16,11 +16,17 @@
 //     admitted as soon as a launch slot and memory free up (continuous
 //     batching);
 //   - reaps finished launches (event query), unpins their slots and reports
-//     each request's submit, launch and completion times.
+//     each request's submit, launch and completion times;
+//   - optionally runs the streaming policy of Section 3.4 (an implicit chunk
+//     octree cut by the LOD error of Eq. 1) on the recent camera positions,
+//     prefetches the slots it wants into free pool space while nothing
+//     waits, and evicts slots it does not want first.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -71,10 +77,17 @@ struct svd_server {
   uint64_t use_seq = 0;
   uint64_t data_bytes = 0;           // pool bytes of resident chunk LODs
   hipStream_t up = nullptr;          // uploads and descriptor writes
-  hipEvent_t up_done = nullptr;      // after the latest admission's uploads
-  bool up_pending = false;
+  hipEvent_t up_done = nullptr;      // recorded on `up` before a launch that follows new uploads
+  bool up_dirty = false;             // uploads enqueued since up_done was last recorded
+  bool up_pending = false;           // up_done has been recorded
   hipStream_t plain = nullptr;       // plain mode: every launch (the world has one view table)
   std::vector<Flight> fl;
+  // streaming policy
+  std::deque<std::array<int64_t, 4>> recent;  // last camera positions (2^16 units) and their chunk
+  std::vector<uint8_t> wanted;               // per slot
+  std::vector<uint32_t> want_order;          // wanted slots: coarse LODs first, then nearer first
+  size_t want_next = 0;
+  bool want_dirty = false;
 
   std::mutex mu;                     // guards everything below
   std::condition_variable wake;      // worker: submissions, stop
@@ -115,14 +128,18 @@ static void unpin(svd_server* s, const std::vector<uint32_t>& slots) {
   for (uint32_t sl : slots) s->pins[sl]--;
 }
 
-// Evict the least recently used resident slot that nobody pins; false if
-// there is none.
+// Evict the least recently used resident slot that nobody pins, taking slots
+// the streaming policy does not want before those it wants; false if there
+// is none.
 static bool evict_one(svd_server* s) {
   svd_world* w = s->w;
   size_t best = SIZE_MAX;
-  for (size_t i = 0; i < w->slot.size(); i++) {
-    if (w->slot[i].state != svd_world::kResident || !w->slot[i].bytes || s->pins[i]) continue;
-    if (best == SIZE_MAX || s->last_use[i] < s->last_use[best]) best = i;
+  for (int pass = 0; pass < 2 && best == SIZE_MAX; pass++) {
+    for (size_t i = 0; i < w->slot.size(); i++) {
+      if (w->slot[i].state != svd_world::kResident || !w->slot[i].bytes || s->pins[i]) continue;
+      if (pass == 0 && !s->wanted.empty() && s->wanted[i]) continue;
+      if (best == SIZE_MAX || s->last_use[i] < s->last_use[best]) best = i;
+    }
   }
   if (best == SIZE_MAX) return false;
   const size_t bytes = w->slot[best].bytes;
@@ -133,6 +150,150 @@ static bool evict_one(svd_server* s) {
   s->st.evict_bytes += bytes;
   s->st.pool_used = s->data_bytes;
   return true;
+}
+
+// Streaming policy (Section 3.4): walk an implicit octree over the chunk
+// grid from each recent camera.  A node at level n covers 2^n chunks per
+// axis.  LODs are per-chunk pyramids here, chosen by Eq. 1's distance rule,
+// so the policy's LOD for a chunk at centre distance d is
+//   LOD_f(d) = number of thresholds T with d >= T f   (f = streaming factor),
+// the chunk's Eq. 1 LOD with every threshold stretched by f (f > 1 loads
+// finer LODs farther out, ahead of a camera that approaches).  A node is
+// split while a chunk in it could still get an LOD finer than the node's
+// own (its LOD error, threshold x f - distance to the node, is positive);
+// the chunks of a node that is not split are wanted at LOD_f and at their
+// exact current LOD.  Wanted slots are ordered coarse LODs first, then
+// nearer chunks first.
+static uint32_t lod_at(const svd_world* w, double d, double f) {
+  uint32_t k = 0;
+  for (uint32_t j = 0; j + 1 < w->desc.lod_count; j++)
+    if (d >= (double)w->desc.lod_threshold[j] * f) k++;
+  return k;
+}
+
+static void policy_node(svd_server* s, const double cam[3], int n, const int64_t c[3],
+                        std::vector<std::pair<double, uint32_t>>& out) {
+  const svd_world* w = s->w;
+  const int64_t span = (int64_t)1 << n;
+  for (int a = 0; a < 3; a++)
+    if (c[a] >= (int64_t)w->desc.grid[a]) return;
+  const double S = (double)((int64_t)1 << w->desc.chunk_log2);
+  const double f = s->d.streaming_factor;
+  const int nl = (int)w->desc.lod_count;
+  const int own = std::min(n, nl - 1);  // the LOD a node of this size stands for
+  bool split = false;
+  if (n > 0) {
+    if (n > nl - 1) {
+      split = true;  // no LOD this coarse: always refine
+    } else {
+      double d2 = 0;  // camera to the node's box (clipped to the grid)
+      for (int a = 0; a < 3; a++) {
+        const int64_t hi = std::min<int64_t>(c[a] + span, w->desc.grid[a]);
+        const double lo_v = (double)c[a] * S, hi_v = (double)hi * S;
+        const double e = cam[a] < lo_v ? lo_v - cam[a] : (cam[a] > hi_v ? cam[a] - hi_v : 0.0);
+        d2 += e * e;
+      }
+      split = (double)w->desc.lod_threshold[own - 1] * std::max(f, 1.0) - std::sqrt(d2) > 0;  // LOD error
+    }
+  }
+  if (split) {
+    const int64_t h = span / 2;
+    for (int o = 0; o < 8; o++) {
+      const int64_t cc[3] = {c[0] + ((o & 1) ? h : 0), c[1] + ((o & 2) ? h : 0), c[2] + ((o & 4) ? h : 0)};
+      policy_node(s, cam, n - 1, cc, out);
+    }
+    return;
+  }
+  for (int64_t z = c[2]; z < std::min<int64_t>(c[2] + span, w->desc.grid[2]); z++)
+    for (int64_t y = c[1]; y < std::min<int64_t>(c[1] + span, w->desc.grid[1]); y++)
+      for (int64_t x = c[0]; x < std::min<int64_t>(c[0] + span, w->desc.grid[0]); x++) {
+        const uint32_t ci = (uint32_t)(x + w->desc.grid[0] * (y + w->desc.grid[1] * z));
+        const double dx = (x + 0.5) * S - cam[0], dy = (y + 0.5) * S - cam[1], dz = (z + 0.5) * S - cam[2];
+        const double d = std::sqrt(dx * dx + dy * dy + dz * dz);
+        const uint32_t ks[2] = {lod_at(w, d, f), lod_at(w, d, 1.0)};
+        for (uint32_t k : ks) {
+          const uint32_t sl = ci * 4 + k;
+          if (s->wanted[sl] || !s->src[ci]->lod[k].n_solid) continue;
+          s->wanted[sl] = 1;
+          out.push_back({(double)(nl - 1 - (int)k) * 1e12 + d, sl});
+        }
+      }
+}
+
+static void run_policy(svd_server* s) {
+  const svd_world* w = s->w;
+  std::fill(s->wanted.begin(), s->wanted.end(), 0);
+  std::vector<std::pair<double, uint32_t>> list;
+  int levels = 0;
+  while (((int64_t)1 << levels) < (int64_t)std::max({w->desc.grid[0], w->desc.grid[1], w->desc.grid[2]})) levels++;
+  for (const auto& r : s->recent) {
+    const double cam[3] = {r[0] / 65536.0, r[1] / 65536.0, r[2] / 65536.0};
+    const int64_t root[3] = {0, 0, 0};
+    policy_node(s, cam, levels, root, list);
+  }
+  std::sort(list.begin(), list.end());
+  s->want_order.clear();
+  for (const auto& e : list) s->want_order.push_back(e.second);
+  s->want_next = 0;
+  s->want_dirty = false;
+}
+
+// Note the camera of an admitted request; a chunk not among the last 8
+// cameras' chunks re-runs the policy.
+static void note_camera(svd_server* s, const svd_ray_frame& f) {
+  if (!(s->d.streaming_factor > 0)) return;
+  const svd_world* w = s->w;
+  int64_t cc[3];
+  for (int a = 0; a < 3; a++) cc[a] = (f.O[a] >> 16) >> w->desc.chunk_log2;
+  const int64_t key = cc[0] + 65536 * (cc[1] + 65536 * cc[2]);
+  for (const auto& r : s->recent)
+    if (r[3] == key) return;
+  s->recent.push_back({f.O[0], f.O[1], f.O[2], key});
+  if (s->recent.size() > 8) s->recent.pop_front();
+  s->want_dirty = true;
+}
+
+// Upload up to 4 wanted slots into free space; false when there is nothing
+// left to do.
+static bool prefetch(svd_server* s) {
+  if (!(s->d.streaming_factor > 0)) return false;
+  if (s->want_dirty) run_policy(s);
+  svd_world* w = s->w;
+  size_t free_bytes = 0, largest = 0;
+  for (const auto& fb : w->free_blocks) {
+    free_bytes += fb.second;
+    largest = std::max(largest, fb.second);
+  }
+  const size_t reserve = (w->pool_bytes - w->data_begin) / 8;
+  int n = 0;
+  while (s->want_next < s->want_order.size() && n < 4) {
+    const uint32_t sl = s->want_order[s->want_next];
+    if (w->slot[sl].state == svd_world::kResident) {
+      s->want_next++;
+      continue;
+    }
+    const LodData& L = s->src[sl / 4]->lod[sl % 4];
+    const size_t bytes = L.off_end - L.off_begin;
+    if (free_bytes < reserve + bytes || largest < bytes) {  // full: stop until the policy changes
+      s->want_next = s->want_order.size();
+      break;
+    }
+    if (world_upload_lods(w, sl / 4, s->src[sl / 4], 1u << (sl % 4), s->up) != SVD_OK) {
+      s->want_next = s->want_order.size();
+      break;
+    }
+    s->want_next++;
+    s->last_use[sl] = ++s->use_seq;
+    free_bytes -= bytes;
+    n++;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->data_bytes += bytes;
+    s->st.prefetches++;
+    s->st.prefetch_bytes += bytes;
+    s->st.pool_used = s->data_bytes;
+  }
+  if (n) s->up_dirty = true;
+  return n > 0;
 }
 
 // Make every slot of r resident and pinned.  `others` = launches or
@@ -190,13 +351,7 @@ static int admit(svd_server* s, Request& r, bool others) {
     while (evict_one(s)) {  // nobody pins anything: start from an empty pool
     }
   }
-  if (uploaded) {  // every launch from now on waits for these copies
-    if (hipEventRecord(s->up_done, s->up) != hipSuccess) {
-      if (rc == SVD_OK) unpin(s, r.need);
-      return svd_fail(SVD_EDEVICE, "serve: upload event");
-    }
-    s->up_pending = true;
-  }
+  if (uploaded) s->up_dirty = true;  // the next launch waits for these copies
   if (rc == SVD_ENOMEM) return others ? kWait : svd_fail(SVD_ENOMEM, "serve: the view needs more than the whole pool");
   if (rc) return rc;
   for (uint32_t sl : r.need) s->last_use[sl] = ++s->use_seq;
@@ -224,6 +379,11 @@ static bool reap(svd_server* s) {
 }
 
 static int enqueue(svd_server* s, Flight& f) {
+  if (s->up_dirty) {  // every upload enqueued so far lands before this launch reads the pool
+    if (hipEventRecord(s->up_done, s->up) != hipSuccess) return svd_fail(SVD_EDEVICE, "serve: upload event");
+    s->up_dirty = false;
+    s->up_pending = true;
+  }
   if (s->up_pending && hipStreamWaitEvent(f.stream, s->up_done, 0) != hipSuccess)
     return svd_fail(SVD_EDEVICE, "serve: stream wait");
   int rc = SVD_OK;
@@ -271,6 +431,7 @@ static bool launch(svd_server* s) {
         continue;
       }
       rays += px;
+      note_camera(s, r.frame);
       take.push_back(std::move(r));
       s->pending.pop_front();
     }
@@ -304,7 +465,9 @@ static void worker(svd_server* s) {
         s->pending.push_back(std::move(s->inbox.front()));
         s->inbox.pop_front();
       }
-      if (s->pending.empty() && !any_busy(s)) {
+      const bool prefetch_left =
+          s->d.streaming_factor > 0 && (s->want_dirty || s->want_next < s->want_order.size());
+      if (s->pending.empty() && !any_busy(s) && !prefetch_left) {
         if (s->stop) break;
         s->wake.wait(lk, [s] { return s->stop || !s->inbox.empty(); });
         continue;
@@ -312,7 +475,8 @@ static void worker(svd_server* s) {
     }
     const bool a = reap(s);
     const bool b = launch(s);
-    if (!a && !b) std::this_thread::yield();  // launches in flight: poll their events
+    const bool c = s->pending.empty() && prefetch(s);  // streaming policy, while nothing waits
+    if (!a && !b && !c) std::this_thread::yield();  // launches in flight: poll their events
   }
 }
 
@@ -335,6 +499,8 @@ extern "C" int svd_server_create(svd_world* w, const svd_server_desc* d, svd_ser
   if (d->inflight < 1 || d->inflight > 8) return svd_fail(SVD_EINVAL, "serve: inflight must be 1..8");
   if (d->mode == SVD_SERVE_BATCHED && (d->max_views < 1 || d->max_views > 1024 || d->max_rays < 1))
     return svd_fail(SVD_EINVAL, "serve: max_views must be 1..1024 and max_rays >= 1");
+  if (!(d->streaming_factor >= 0.0f && d->streaming_factor <= 1e6f) || d->reserved)
+    return svd_fail(SVD_EINVAL, "serve: streaming_factor must be in [0, 1e6] and reserved 0");
   svd_server* s = new (std::nothrow) svd_server();
   if (!s) return svd_fail(SVD_ENOMEM, "serve: out of host memory");
   s->w = w;
@@ -345,6 +511,7 @@ extern "C" int svd_server_create(svd_world* w, const svd_server_desc* d, svd_ser
     if (sl.state == svd_world::kResident) s->data_bytes += sl.bytes;
   s->st.pool_used = s->data_bytes;
   s->src.assign(w->nchunks, nullptr);
+  s->wanted.assign(w->slot.size(), 0);
   s->pins.assign(w->slot.size(), 0);
   s->last_use.assign(w->slot.size(), 0);
   hipError_t e = hipGetDevice(&s->device);

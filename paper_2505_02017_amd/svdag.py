@@ -70,7 +70,8 @@ class svd_ray_frame(ctypes.Structure):
 class svd_server_desc(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_uint32), ("max_views", ctypes.c_uint32), ("inflight", ctypes.c_uint32),
                 ("tile_w", ctypes.c_uint32), ("claim", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
-                ("max_rays", ctypes.c_uint64)]
+                ("max_rays", ctypes.c_uint64), ("streaming_factor", ctypes.c_float),
+                ("reserved", ctypes.c_uint32)]
 
 
 class svd_request_done(ctypes.Structure):
@@ -81,7 +82,7 @@ class svd_request_done(ctypes.Structure):
 class svd_server_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "submitted", "completed", "failed", "launches", "uploads", "upload_bytes", "evictions",
-        "evict_bytes", "memory_waits", "pool_used")]
+        "evict_bytes", "memory_waits", "pool_used", "prefetches", "prefetch_bytes")]
 
 
 class svd_blob_stats(ctypes.Structure):
@@ -524,9 +525,10 @@ class Server:
 
 
 def svd_server_create(w: World, mode: int = SVD_SERVE_BATCHED, max_views: int = 64, inflight: int = 2,
-                      max_rays: int = 1 << 24, tile_w: int = 0, claim: int = 0, blocks_per_cu: int = 0) -> Server:
+                      max_rays: int = 1 << 24, tile_w: int = 0, claim: int = 0, blocks_per_cu: int = 0,
+                      streaming_factor: float = 0.0) -> Server:
     d = svd_server_desc(mode=mode, max_views=max_views, inflight=inflight, tile_w=tile_w, claim=claim,
-                        blocks_per_cu=blocks_per_cu, max_rays=max_rays)
+                        blocks_per_cu=blocks_per_cu, max_rays=max_rays, streaming_factor=streaming_factor)
     out = ctypes.c_void_p()
     _check(lib().svd_server_create(w.ptr, ctypes.byref(d), ctypes.byref(out)))
     return Server(out.value, w)

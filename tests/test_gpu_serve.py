@@ -121,9 +121,10 @@ def test_lod_residency_marks_not_loaded(env, world):
     assert e.value.code == svdag.SVD_EINVAL
 
 
-def _serve(svdag, torch, sw, blobs, cams, mode, views, inflight, budget, flags, seed):
+def _serve(svdag, torch, sw, blobs, cams, mode, views, inflight, budget, flags, seed, sf=0.0):
     w = _server_world(svdag, torch, sw, budget, views, inflight)
-    s = svdag.svd_server_create(w, mode=mode, max_views=views, inflight=inflight, max_rays=40000)
+    s = svdag.svd_server_create(w, mode=mode, max_views=views, inflight=inflight, max_rays=40000,
+                                streaming_factor=sf)
     for ci, b in blobs.items():
         svdag.svd_server_set_chunk(s, _coords(sw, ci), b)
     outs = [torch.full((c.width * c.height, 4), -1, dtype=torch.int32, device="cuda") for c in cams]
@@ -144,9 +145,10 @@ def _serve(svdag, torch, sw, blobs, cams, mode, views, inflight, budget, flags, 
     return w, outs, done, stats
 
 
-@pytest.mark.parametrize("mode,views,inflight,tight", [(0, 8, 2, False), (0, 8, 2, True), (0, 3, 3, True),
-                                                       (1, 1, 3, True)])
-def test_server_results_equal_alone(env, world, mode, views, inflight, tight):
+@pytest.mark.parametrize("mode,views,inflight,tight,sf", [(0, 8, 2, False, 0.0), (0, 8, 2, True, 0.0),
+                                                          (0, 3, 3, True, 0.0), (1, 1, 3, True, 0.0),
+                                                          (0, 8, 2, False, 2.0), (0, 4, 2, True, 1.5)])
+def test_server_results_equal_alone(env, world, mode, views, inflight, tight, sf):
     svdag, torch = env
     sw, blobs, ref_w = world
     flags = svdag.SVD_NO_CULL
@@ -157,8 +159,9 @@ def test_server_results_equal_alone(env, world, mode, views, inflight, tight):
     union = set().union(*needs)
     total = sum((sb[x] + 255) // 256 * 256 for x in union)
     budget = max(per) if tight else sum((v + 255) // 256 * 256 for v in sb.values())
-    note(f"mode {mode} views {views} inflight {inflight}: budget {budget}, largest view {max(per)}, union {total}")
-    w, outs, done, st = _serve(svdag, torch, sw, blobs, cams, mode, views, inflight, budget, flags, 3)
+    note(f"mode {mode} views {views} inflight {inflight} streaming factor {sf}: budget {budget}, "
+         f"largest view {max(per)}, union {total}")
+    w, outs, done, st = _serve(svdag, torch, sw, blobs, cams, mode, views, inflight, budget, flags, 3, sf)
     note(f"stats {st}")
     assert len(done) == len(cams) and sorted(d["tag"] for d in done) == list(range(len(cams)))
     assert all(d["status"] == 0 for d in done), [d for d in done if d["status"]]
@@ -168,7 +171,12 @@ def test_server_results_equal_alone(env, world, mode, views, inflight, tight):
     for i, c in enumerate(cams):
         assert np.array_equal(outs[i].cpu().numpy(), _alone(svdag, torch, ref_w, c, flags)), f"request {i}"
     assert st["completed"] == len(cams) and st["failed"] == 0
-    assert st["uploads"] >= len(union) and st["upload_bytes"] >= total
+    assert st["uploads"] + st["prefetches"] >= len(union)
+    assert st["upload_bytes"] + st["prefetch_bytes"] >= total
+    if sf > 0:
+        assert st["prefetches"] > 0
+    else:
+        assert st["prefetches"] == 0
     if total > budget:
         assert st["evictions"] > 0
     assert st["pool_used"] <= budget
