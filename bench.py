@@ -286,6 +286,9 @@ def main():
             "bytes_per_ray": round(mean_b, 2),
             "bytes_per_launch": round(bytes_per_launch), "launch_ms": round(float(pass_ms.mean()), 4),
         }
+        if "l1_hit_rate" in prof:
+            result["caches"] = {"l1_hit_rate": float(prof["l1_hit_rate"]), "l2_hit_rate": float(prof["l2_hit_rate"]),
+                                "source": "rocprofv3 TCP/TCC counters in profiles/ (same kernel source)"}
         if "valu_insts_per_launch" in prof:
             # VALU issue view: wave instructions per second over the issue peak
             # (1024 SIMDs x 2.4 GHz / 4 cycles per wave64 VALU instruction)

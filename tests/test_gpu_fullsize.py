@@ -1,6 +1,8 @@
-"""GPU parity at full workload sizes, in the launch configuration bench.py
-times (svd_view_stage + svd_view_trace on torch's stream): whole frames
-compared with the oracle, plus properties checked on every pixel."""
+"""GPU parity at full workload sizes, in the launch configurations bench.py
+times: per-view frames (svd_view_stage + svd_view_trace on torch's stream)
+compared whole with the oracle, plus properties checked on every pixel; the
+64-view mixed batch (tuned graph launch) and served requests over a pool
+holding a quarter of the map, compared with the oracle on sampled pixels."""
 import os
 import time
 from concurrent.futures import ThreadPoolExecutor
@@ -26,9 +28,9 @@ def env():
     return svdag, torch
 
 
-def _build(svdag, torch, kind, seed, lod_count, thr, nviews):
+def _build(svdag, torch, kind, seed, lod_count, thr, nviews, extra_cams=()):
     """Generate every chunk once; library blobs for all LODs, oracle DAGs only
-    for the LODs the first `nviews` views pick."""
+    for the LODs that the first `nviews` views and `extra_cams` pick."""
     sw = scenes.SceneWorld(kind, seed)
     CL, (gx, gy, gz) = sw.chunk_log2, sw.grid
     nch = gx * gy * gz
@@ -36,7 +38,8 @@ def _build(svdag, torch, kind, seed, lod_count, thr, nviews):
     ow = oracle.World(CL, sw.grid, lod_count)
     frames = [oracle.camera_frame(c) for c in cams]
     vlods = [ow.lod_pick(f.O, thr) for f in frames]
-    need = [sorted({int(v[ci]) for v in vlods}) for ci in range(nch)]
+    xlods = [ow.lod_pick(oracle.camera_frame(c).O, thr) for c in extra_cams]
+    need = [sorted({int(v[ci]) for v in vlods + xlods}) for ci in range(nch)]
     t0 = time.time()
 
     def work(ci):
@@ -55,12 +58,13 @@ def _build(svdag, torch, kind, seed, lod_count, thr, nviews):
     note(f"{kind}: built {nch} chunks in {time.time() - t0:.1f}s")
     desc = svdag.make_desc(CL, sw.grid, lod_count, thr)
     dev = sum(svdag.svd_blob_stats_get(b, k)["device_bytes"] for b in blobs.values() for k in range(lod_count))
-    pool = torch.empty(svdag.table_bytes(sw.grid) + dev + 256 * nch, dtype=torch.uint8, device="cuda")
+    pool = torch.empty(svdag.table_bytes(sw.grid) + dev + 256 * nch + svdag.batch_bytes(nch, 64),
+                       dtype=torch.uint8, device="cuda")
     w = svdag.svd_world_create(desc, pool)
     for c, b in blobs.items():
         svdag.svd_chunk_upload(w, c, b)
     torch.cuda.synchronize()
-    return sw, w, ow, cams, frames, vlods
+    return sw, w, ow, cams, frames, vlods, blobs
 
 
 def _trace_like_bench(svdag, torch, w, cam):
@@ -93,7 +97,7 @@ def _properties(svdag, raw, vt, sw):
 def test_terrain1024_full_frames(env):
     svdag, torch = env
     note("terrain1024: one 1024^3 chunk, 1920x1080")
-    sw, w, ow, cams, frames, vlods = _build(svdag, torch, "terrain1024", 2025, 1, (256, 1024, 4096), 2)
+    sw, w, ow, cams, frames, vlods, _ = _build(svdag, torch, "terrain1024", 2025, 1, (256, 1024, 4096), 2)
     for v in range(2):
         raw, vt = _trace_like_bench(svdag, torch, w, cams[v])
         _properties(svdag, raw, vt, sw)
@@ -104,10 +108,42 @@ def test_terrain1024_full_frames(env):
         assert n > 0.3 * ref.size
 
 
-def test_map512_full_frames(env):
+THR = (256, 1024, 4096)
+SIZES = [(320, 180), (640, 360), (1280, 720), (1920, 1080)]
+
+
+def _batch_cams(sw, n=64, seed=2025):
+    """The batched workload: n seeded poses, resolutions uniform over SIZES."""
+    rng = np.random.default_rng([seed, 64])
+    cams = []
+    for i in range(n):
+        W, H = SIZES[int(rng.integers(0, len(SIZES)))]
+        cams.append(sw.views(1, 1000 + i, W, H)[0])
+    return cams
+
+
+@pytest.fixture(scope="module")
+def map512(env):
     svdag, torch = env
-    note("map512: 16x16 chunks of 512^3, 4 LODs, 2560x1440")
-    sw, w, ow, cams, frames, vlods = _build(svdag, torch, "map512", 2025, 4, (256, 1024, 4096), 3)
+    note("map512: 16x16 chunks of 512^3, 4 LODs")
+    sw0 = scenes.SceneWorld("map512", 2025)
+    extra = _batch_cams(sw0) + [c for _, c in sw0.walk_requests(8, 2000.0, 0.05, seed=7, speed=600.0)]
+    return _build(svdag, torch, "map512", 2025, 4, THR, 3, extra)
+
+
+def _sampled(svdag, ow, raw, cam, n, label, rng):
+    """Compare n sampled pixels of a view (its corners included) with the oracle."""
+    fr = oracle.camera_frame(cam)
+    npx = cam.width * cam.height
+    idx = np.unique(np.concatenate([[0, cam.width - 1, npx - cam.width, npx - 1],
+                                    rng.integers(0, npx, min(n, npx))])).astype(np.uint32)
+    ref = ow.trace_frame(ow.lod_pick(fr.O, THR), fr, idx, mode=1, threads=NT)
+    return compare(svdag, raw, ref, idx=idx, label=label)
+
+
+def test_map512_full_frames(env, map512):
+    svdag, torch = env
+    sw, w, ow, cams, frames, vlods, _ = map512
     lods_seen = set()
     for v in range(3):
         raw, vt = _trace_like_bench(svdag, torch, w, cams[v])
@@ -119,3 +155,64 @@ def test_map512_full_frames(env):
         compare(svdag, raw, ref, label=f"map512 view {v}")
         lods_seen |= set(ref["lod"][ref["hit"] == 1].tolist())
     assert len(lods_seen) >= 2
+
+
+def test_map512_batch_of_64_sampled(env, map512):
+    """The 64-view mixed batch in the bench's launch configuration (tuned
+    tiling and occupancy, one graph launch) against the oracle."""
+    svdag, torch = env
+    sw, w, ow, cams, frames, vlods, _ = map512
+    bc = _batch_cams(sw)
+    nrec = svdag.batch_records(bc)
+    b = svdag.svd_batch_create(w, len(bc))
+    out = torch.empty((nrec, 4), dtype=torch.int32, device="cuda")
+    tw, claim, occ, ms = svdag.svd_batch_tune(b, bc, out, reps=1)
+    note(f"batch of {len(bc)} views ({nrec} rays): tile {tw}x{64 // tw}, claim {claim}, {occ}/CU, {ms:.2f} ms")
+    out.fill_(-1)
+    svdag.svd_batch_trace(b, bc, out)
+    torch.cuda.synchronize()
+    raw = out.cpu().numpy()
+    svdag.svd_batch_destroy(b)
+    rng = np.random.default_rng(64)
+    off, hits = 0, 0
+    for v, c in enumerate(bc):
+        n = c.width * c.height
+        hits += _sampled(svdag, ow, raw[off:off + n], c, 1500, f"batch view {v} ({c.width}x{c.height})", rng)
+        off += n
+    assert hits > 0
+
+
+def test_map512_served_sampled(env, map512):
+    """Requests served through a pool holding a quarter of the map's bytes
+    (uploads, evictions, prefetch, batched launches) against the oracle."""
+    svdag, torch = env
+    sw, w_full, ow, cams, frames, vlods, blobs = map512
+    sched = sw.walk_requests(8, 2000.0, 0.05, seed=7, speed=600.0)
+    nch = sw.grid[0] * sw.grid[1] * sw.grid[2]
+    all_bytes = sum((svdag.svd_blob_stats_get(b, k)["device_bytes"] + 255) // 256 * 256
+                    for b in blobs.values() for k in range(4))
+    budget = all_bytes // 4 // 256 * 256
+    pool = torch.empty(svdag.table_bytes(sw.grid) + 2 * svdag.batch_bytes(nch, 16) + budget,
+                       dtype=torch.uint8, device="cuda")
+    w = svdag.svd_world_create(svdag.make_desc(sw.chunk_log2, sw.grid, 4, THR), pool)
+    s = svdag.svd_server_create(w, max_views=16, inflight=2, max_rays=1 << 23, streaming_factor=1.5)
+    for c, b in blobs.items():
+        svdag.svd_server_set_chunk(s, c, b)
+    outs = [torch.empty((c.width * c.height, 4), dtype=torch.int32, device="cuda") for _, c in sched]
+    torch.cuda.synchronize()
+    note(f"serving {len(sched)} requests, pool {budget >> 20} MiB of {all_bytes >> 20} MiB")
+    t0 = time.perf_counter()
+    for i, (t, c) in enumerate(sched):
+        while time.perf_counter() - t0 < t:
+            pass
+        svdag.svd_server_submit(s, c, outs[i], tag=i)
+    done = []
+    while len(done) < len(sched) and time.perf_counter() - t0 < 60:
+        done += svdag.svd_server_poll(s, 256, wait_us=100000)
+    st = svdag.svd_server_stats_get(s)
+    svdag.svd_server_destroy(s)
+    note(f"served: {st}")
+    assert len(done) == len(sched) and all(d["status"] == 0 for d in done)
+    rng = np.random.default_rng(7)
+    for i, (_, c) in enumerate(sched):
+        _sampled(svdag, ow, outs[i].cpu().numpy(), c, 1500, f"request {i} ({c.width}x{c.height})", rng)
