@@ -456,6 +456,11 @@ static bool launch(svd_server* s) {
   return progress;
 }
 
+static bool stopping(svd_server* s) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  return s->stop;
+}
+
 static void worker(svd_server* s) {
   hipSetDevice(s->device);
   for (;;) {
@@ -465,8 +470,8 @@ static void worker(svd_server* s) {
         s->pending.push_back(std::move(s->inbox.front()));
         s->inbox.pop_front();
       }
-      const bool prefetch_left =
-          s->d.streaming_factor > 0 && (s->want_dirty || s->want_next < s->want_order.size());
+      const bool prefetch_left = !s->stop && s->d.streaming_factor > 0 &&
+                                 (s->want_dirty || s->want_next < s->want_order.size());
       if (s->pending.empty() && !any_busy(s) && !prefetch_left) {
         if (s->stop) break;
         s->wake.wait(lk, [s] { return s->stop || !s->inbox.empty(); });
@@ -475,7 +480,7 @@ static void worker(svd_server* s) {
     }
     const bool a = reap(s);
     const bool b = launch(s);
-    const bool c = s->pending.empty() && prefetch(s);  // streaming policy, while nothing waits
+    const bool c = s->pending.empty() && !stopping(s) && prefetch(s);  // streaming policy, while nothing waits
     if (!a && !b && !c) std::this_thread::yield();  // launches in flight: poll their events
   }
 }
