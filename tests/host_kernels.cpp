@@ -1,0 +1,138 @@
+// Test infrastructure: the library's kernel logic (chunk stage, beam pass,
+// per-pixel trace from kernels.hip) run on the host over the same device
+// images, so CPU-only test runs check it against the oracle.  Not part of
+// libsvdag; nothing here touches a GPU.
+#include "kernels.hip"
+
+#include <algorithm>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+using namespace svd;
+
+struct HkWorld {
+  svd_world_desc desc;
+  uint32_t n = 0;
+  std::vector<DevDag> tab;                   // descriptor table, addresses into `image`
+  std::vector<std::vector<uint8_t>> image;   // per chunk: the blob's device image
+};
+
+extern "C" HkWorld* hk_world_new(const svd_world_desc* d) {
+  HkWorld* w = new HkWorld();
+  w->desc = *d;
+  w->n = d->grid[0] * d->grid[1] * d->grid[2];
+  w->tab.assign((size_t)w->n * 4, DevDag());
+  memset(w->tab.data(), 0, w->tab.size() * sizeof(DevDag));
+  w->image.resize(w->n);
+  return w;
+}
+
+extern "C" void hk_world_free(HkWorld* w) { delete w; }
+
+// All LODs of b as chunk ci (a copy of its device image), or only their
+// descriptions (addresses zero) when `describe_only`.
+extern "C" int hk_upload(HkWorld* w, uint32_t ci, const svd_blob* b, int describe_only) {
+  if (ci >= w->n || b->lod_count != w->desc.lod_count) return SVD_EINVAL;
+  w->image[ci] = b->image;
+  const uint64_t base = (uint64_t)(uintptr_t)w->image[ci].data();
+  for (uint32_t k = 0; k < 4; k++) {
+    DevDag& d = w->tab[(size_t)ci * 4 + k];
+    memset(&d, 0, sizeof(d));
+    if (k >= b->lod_count) continue;
+    const LodData& L = b->lod[k];
+    if (!describe_only) {
+      d.nodes = base + L.off_nodes;
+      d.leaves = base + L.off_leaves;
+      d.pre = base + L.off_pre;
+      d.rle_start = base + L.off_rle_start;
+      d.rle_mat = base + L.off_rle_mat;
+    }
+    d.rle_n = (uint32_t)L.rle_start.size();
+    d.root = L.root_word;
+    d.solid = L.n_solid;
+    for (int a = 0; a < 3; a++) {
+      d.lo[a] = L.lo[a];
+      d.hi[a] = L.hi[a];
+    }
+  }
+  return SVD_OK;
+}
+
+// Stage, optional beam pass (16x4 tiles, as the per-view launch) and trace
+// of every pixel; records in `out` (width*height x 16 bytes), the view table
+// in `view_out` (may be NULL).
+extern "C" int hk_trace(HkWorld* w, const svd_ray_frame* f, uint32_t flags, svd_hit* out, uint32_t* view_out,
+                        uint32_t threads) {
+  StageParams sp;
+  memset(&sp, 0, sizeof(sp));
+  memcpy(sp.O, f->O, sizeof(sp.O));
+  sp.cull = !(flags & SVD_NO_CULL) && cull_planes(f, sp.n);
+  memcpy(sp.grid, w->desc.grid, sizeof(sp.grid));
+  sp.chunk_log2 = w->desc.chunk_log2;
+  sp.lod_count = w->desc.lod_count;
+  memcpy(sp.thr, w->desc.lod_threshold, sizeof(sp.thr));
+  sp.nchunks = w->n;
+  sp.desc = w->tab.data();
+  std::vector<uint32_t> view(w->n);
+  for (uint32_t ci = 0; ci < w->n; ci++) view[ci] = host_stage_chunk(sp, ci);
+  if (view_out) memcpy(view_out, view.data(), w->n * 4);
+
+  const uint32_t W = f->width, H = f->height;
+  const uint32_t tw = kViewTileW, th = 64 / kViewTileW;
+  const uint32_t tiles_x = (W + tw - 1) / tw, tiles_y = (H + th - 1) / th;
+  std::vector<uint32_t> start((size_t)tiles_x * tiles_y, 0);
+  BeamParams bp;
+  memset(&bp, 0, sizeof(bp));
+  memcpy(bp.O, f->O, sizeof(bp.O));
+  memcpy(bp.A, f->A, sizeof(bp.A));
+  memcpy(bp.BX, f->BX, sizeof(bp.BX));
+  memcpy(bp.BY, f->BY, sizeof(bp.BY));
+  bp.W = W;
+  bp.H = H;
+  memcpy(bp.grid, w->desc.grid, sizeof(bp.grid));
+  bp.chunk_log2 = w->desc.chunk_log2;
+  bp.view = view.data();
+  bp.desc = w->tab.data();
+  TraceParams tp;
+  memset(&tp, 0, sizeof(tp));
+  memcpy(tp.O, f->O, sizeof(tp.O));
+  memcpy(tp.A, f->A, sizeof(tp.A));
+  memcpy(tp.BX, f->BX, sizeof(tp.BX));
+  memcpy(tp.BY, f->BY, sizeof(tp.BY));
+  tp.W = W;
+  tp.H = H;
+  memcpy(tp.grid, w->desc.grid, sizeof(tp.grid));
+  tp.chunk_log2 = w->desc.chunk_log2;
+  tp.view = view.data();
+  tp.desc = w->tab.data();
+
+  const uint32_t nt = std::max(1u, std::min(threads, 64u));
+  auto run_rows = [&](uint32_t t0) {
+    for (uint32_t ty = t0; ty < tiles_y; ty += nt) {
+      for (uint32_t tx = 0; tx < tiles_x; tx++) {
+        uint32_t s = 0;
+        if (flags & SVD_BEAM) {
+          uint32_t bstk[2 * 8];
+          const uint32_t x0 = tx * tw, y0 = ty * th;
+          s = beam_tile(bp, x0, y0, std::min(x0 + tw, W) - 1, std::min(y0 + th, H) - 1, bstk, 1);
+        }
+        start[(size_t)ty * tiles_x + tx] = s;
+        for (uint32_t py = ty * th; py < std::min((ty + 1) * th, H); py++)
+          for (uint32_t px = tx * tw; px < std::min((tx + 1) * tw, W); px++) {
+            uint32_t stk[8];
+            const uint4 r = trace_pixel(tp, px, py, stk, 1, s);
+            svd_hit& h = out[(size_t)py * W + px];
+            h.xy = r.x;
+            h.zf = r.y;
+            memcpy(&h.t, &r.z, 4);
+            h.chunk = r.w;
+          }
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  for (uint32_t t = 0; t < nt; t++) pool.emplace_back(run_rows, t);
+  for (auto& t : pool) t.join();
+  return SVD_OK;
+}

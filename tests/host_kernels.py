@@ -1,0 +1,76 @@
+"""Test infrastructure: ctypes wrapper of host_kernels.cpp (the library's
+kernel logic compiled for the host) and its build step."""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB = os.path.join(HERE, "libhost_kernels.so")
+
+
+def build(verbose: bool = False) -> str:
+    """hipcc the host build of kernels.hip (links libsvdag for the builder)."""
+    pkg = os.path.join(ROOT, "paper_2505_02017_amd")
+    cmd = [os.environ.get("HIPCC", "/opt/rocm/bin/hipcc"), "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread",
+           "-ffp-contract=off", "-x", "hip", "--offload-arch=gfx950",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           f"-I{os.path.join(ROOT, 'include')}", f"-I{os.path.join(pkg, 'csrc')}",
+           os.path.join(HERE, "host_kernels.cpp"), "-o", LIB + ".tmp",
+           f"-L{pkg}", "-lsvdag", f"-Wl,-rpath,{pkg}"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("host kernel build failed:\n" + r.stdout + r.stderr)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise ImportError(f"{LIB} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB)
+        vp, u32 = ctypes.c_void_p, ctypes.c_uint32
+        L.hk_world_new.restype = vp
+        L.hk_world_new.argtypes = [vp]
+        L.hk_world_free.argtypes = [vp]
+        L.hk_world_free.restype = None
+        L.hk_upload.argtypes = [vp, u32, vp, ctypes.c_int]
+        L.hk_trace.argtypes = [vp, vp, u32, vp, vp, u32]
+        _lib = L
+    return _lib
+
+
+class HostWorld:
+    """A world of chunk blobs traced by the host build of the kernels."""
+
+    def __init__(self, svdag, chunk_log2, grid, lod_count, thr, blobs, describe_only=()):
+        self.svdag = svdag
+        self.desc = svdag.make_desc(chunk_log2, grid, lod_count, thr)
+        self.n = grid[0] * grid[1] * grid[2]
+        self._free = lib().hk_world_free
+        self.w = lib().hk_world_new(ctypes.byref(self.desc))
+        self.blobs = blobs
+        for ci, b in blobs.items():
+            assert lib().hk_upload(self.w, ci, b.ptr, int(ci in describe_only)) == 0
+
+    def __del__(self):
+        if getattr(self, "w", None):
+            self._free(self.w)
+            self.w = None
+
+    def trace(self, frame, flags=0, threads=8):
+        out = np.zeros((frame.width * frame.height, 4), np.uint32)
+        view = np.zeros(self.n, np.uint32)
+        assert lib().hk_trace(self.w, ctypes.byref(frame), flags, out.ctypes.data, view.ctypes.data, threads) == 0
+        return out, view

@@ -1,0 +1,94 @@
+"""The library's kernel logic (chunk stage, beam pass, per-pixel trace of
+kernels.hip, compiled for the host by tests/host_kernels.cpp) against the
+oracle, on the CPU: bit-exact records on adversarial frames over tiny
+multi-chunk, multi-LOD worlds and on terrain views; the beam pass and
+culling change no record; a LOD that is only described yields not-loaded
+records, never a read.  The GPU tests check the same code on the device."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import compare
+from paper_2505_02017_amd import scenes
+import test_gpu_parity as gp
+
+NT = min(8, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def env():
+    from paper_2505_02017_amd import svdag
+    import host_kernels
+    if not os.path.exists(host_kernels.LIB):
+        pytest.skip("host kernel build missing: run __graft_entry__.build()")
+    svdag.lib()
+    host_kernels.lib()
+    return svdag, host_kernels
+
+
+@pytest.mark.parametrize("cfg", [
+    (3, (1, 1, 1), 1, 0.3, (256, 1024, 4096)),
+    (3, (2, 2, 1), 1, 0.15, (256, 1024, 4096)),
+    (4, (2, 1, 1), 2, 0.25, (12, 0, 0)),
+    (5, (2, 2, 2), 3, 0.1, (16, 40, 0)),
+    (6, (2, 1, 1), 4, 0.05, (20, 50, 90)),
+])
+def test_adversarial_frames(env, cfg):
+    svdag, hk = env
+    chunk_log2, grid, lod_count, fill, thr = cfg
+    rng = np.random.default_rng(sum(grid) * 1000 + chunk_log2 * 10 + lod_count + 5)
+    S = 1 << chunk_log2
+    nch = grid[0] * grid[1] * grid[2]
+    dense = {ci: scenes.random_grid(rng, S, fill) for ci in range(nch)}
+    blobs = {ci: svdag.svd_chunk_build(g, chunk_log2, lod_count) for ci, g in dense.items()}
+    hw = hk.HostWorld(svdag, chunk_log2, grid, lod_count, thr, blobs)
+    ow = oracle.World(chunk_log2, grid, lod_count)
+    for ci, g in dense.items():
+        ow.add_chunk(ci, g)
+    ext = [g * S for g in grid]
+    hits = 0
+    for i, (O, A, BX, BY, W, H) in enumerate(gp._frames(rng, ext, 150, 16, 8)):
+        fr = svdag.make_frame(O, A, BX, BY, W, H)
+        raw, view = hw.trace(fr, threads=NT)
+        lods = ow.lod_pick(np.array(O, np.int64), thr)
+        assert np.array_equal(view & 3, lods), f"frame {i}: LOD pick"
+        ref = ow.trace_frame(lods, gp._oracle_frame(fr), mode=1, threads=NT)
+        hits += compare(svdag, raw, ref, label=f"{cfg} frame {i}")
+        raw_b, _ = hw.trace(fr, svdag.SVD_BEAM, threads=NT)
+        assert np.array_equal(raw, raw_b), f"{cfg} frame {i}: the beam pass changed a record"
+    assert hits > 0
+
+
+def test_terrain_views_beam_cull_and_not_loaded(env):
+    svdag, hk = env
+    sw = scenes.SceneWorld("custom", 23, chunk_log2=6, grid=(4, 4, 2))
+    dense = {ci: sw.chunk(c) for ci, c in enumerate(sw.chunks())}
+    thr = (48, 96, 160)
+    blobs = {ci: svdag.svd_chunk_build(g, 6, 4) for ci, g in dense.items()}
+    hw = hk.HostWorld(svdag, 6, sw.grid, 4, thr, blobs)
+    ow = oracle.World(6, sw.grid, 4)
+    for ci, g in dense.items():
+        ow.add_chunk(ci, g)
+    half = set(range(0, len(blobs), 2))
+    hw_half = hk.HostWorld(svdag, 6, sw.grid, 4, thr, blobs, describe_only=half)
+    marked = 0
+    for v, cam in enumerate(sw.views(4, 5, 96, 64)):
+        f = svdag.svd_camera_frame(cam)
+        raw, _ = hw.trace(f, threads=NT)
+        for flags in (svdag.SVD_NO_CULL, svdag.SVD_BEAM, svdag.SVD_BEAM | svdag.SVD_NO_CULL):
+            assert np.array_equal(raw, hw.trace(f, flags, threads=NT)[0]), f"view {v} flags {flags}"
+        fr = oracle.camera_frame(cam)
+        compare(svdag, raw, ow.trace_frame(ow.lod_pick(fr.O, thr), fr, mode=1, threads=NT), label=f"terrain {v}")
+        # half the chunks only described: their rays are marked, every other record unchanged
+        for flags in (0, svdag.SVD_BEAM):
+            got, _ = hw_half.trace(f, flags, threads=NT)
+            g = svdag.decode_hits(got)
+            nl = g["chunk"] == svdag.CHUNK_NOT_LOADED
+            assert np.array_equal(got[~nl], raw[~nl]), f"view {v}: a loaded path changed"
+            r = svdag.decode_hits(raw)
+            hit_in_half = (r["hit"] == 1) & np.isin(r["chunk"], list(half))
+            assert np.all(nl[hit_in_half]), f"view {v}: a ray read a chunk that is not loaded"
+            marked += int(nl.sum())
+    assert marked > 0
