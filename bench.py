@@ -67,7 +67,8 @@ def counter_profile(workload):
 
 
 def bytes_per_ray(counts, hits, lods, chunk_log2, n_rle):
-    """Algorithmic bytes of the trace kernel for each ray:
+    """Algorithmic bytes of the trace kernel for each ray (the canonical visit
+    set that the oracle's counting mode replays):
     4 B view entry per chunk visited; 20 B per chunk DAG entered (node and
     leaf array addresses, root word); 4 B child word per internal node
     entered; 12 B (child word + bitmap) per leaf entered; at a hit 28 B
@@ -128,7 +129,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path does not "
-              "shard across GPUs in this build (see DESIGN.md, sharding).", file=sys.stderr)
+              "shard across GPUs here (views would be routed to GPUs by chunk locality; there is no "
+              "multi-GPU code).", file=sys.stderr)
         sys.exit(2)
 
     import torch

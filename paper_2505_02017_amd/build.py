@@ -15,7 +15,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall", "-pthread",
           f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
-# Packed FP32 instructions stay off (toolchain notes).
+# Packed FP32 instructions stay off: some of their forms have returned wrong
+# results on this toolchain without any error.
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 SOURCES = ["builder.cpp", "runtime.cpp", "server.cpp", "kernels.hip"]
 
