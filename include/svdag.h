@@ -161,7 +161,7 @@ typedef struct svd_world svd_world;
 
 /* pool_dev: caller-owned device buffer (e.g. a torch uint8 tensor), 256-byte
  * aligned, that must outlive the world; the library only sub-allocates it.
- * The world's tables take nchunks*4*64 + round256(nchunks*4) + 256 bytes at
+ * The world's tables take nchunks*4*64 + round256(nchunks*4) + 2048 bytes at
  * its start.  Must be called with the pool's device current.  Errors:
  * SVD_EINVAL, SVD_ENOMEM (pool too small for the tables), SVD_EDEVICE. */
 int svd_world_create(const svd_world_desc* desc, void* pool_dev, size_t pool_bytes,
@@ -247,7 +247,7 @@ int svd_view_trace(svd_world* w, const svd_ray_frame* frame, svd_hit* out_dev, v
 
 /* Occupancy of the per-view persistent trace: the grid is blocks_per_cu x
  * (compute units) blocks of 4 waves, but never more waves than the view has
- * 64-pixel tiles.  0 selects the default, 4 blocks per CU (or the most that
+ * 64-pixel tiles.  0 selects the default, 6 blocks per CU (or the most that
  * fit, if fewer); more than fit is SVD_EINVAL.  Results do not depend on it. */
 int svd_world_set_occupancy(svd_world* w, uint32_t blocks_per_cu);
 int svd_world_get_occupancy(const svd_world* w, uint32_t* blocks_per_cu, uint32_t* max_per_cu);
@@ -264,7 +264,7 @@ int svd_view_table(svd_world* w, uint32_t* out, uint32_t n, void* stream);
  * ------------------------------------------------------------------------ */
 typedef struct svd_batch svd_batch;
 
-/* Takes 256 + 256*max_views + 4*max_views*nchunks bytes (rounded to 256)
+/* Takes 2304 + 256*max_views + 4*max_views*nchunks bytes (rounded to 256)
  * from the world's pool and captures the batch's graph.  The batch must be
  * destroyed before its world.  Errors: SVD_EINVAL (max_views 1..65535),
  * SVD_ENOMEM (pool), SVD_EDEVICE. */

@@ -379,23 +379,43 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
   return rec;
 }
 
+// Next tile (or first of `claim` tiles) of the wave from its home queue, or
+// from the following queues once that one is dry; false when all are.
+// Queue q hands out the band [total q / kQueues, total (q + 1) / kQueues).
+__device__ __forceinline__ bool take_tiles(uint32_t* queue, uint32_t total, uint32_t claim, uint32_t home,
+                                           uint32_t lane, uint32_t& qi, uint32_t& t0, uint32_t& t1) {
+  for (; qi < kQueues; qi++) {
+    const uint32_t q = (home + qi) % kQueues;
+    const uint32_t lo = (uint32_t)((uint64_t)total * q / kQueues);
+    const uint32_t hi = (uint32_t)((uint64_t)total * (q + 1) / kQueues);
+    uint32_t t = 0;
+    if (lane == 0) t = atomicAdd(&queue[q * kQueueStride], claim);
+    t = __shfl(t, 0);
+    if (t < hi - lo) {
+      t0 = lo + t;
+      t1 = t0 + claim < hi ? t0 + claim : hi;
+      return true;
+    }
+  }
+  return false;
+}
+
 // Persistent: a machine-filling grid whose waves each take 16x4-pixel tiles
-// from a counter until the image is done, so that no wave idles while the
-// slower waves of its work-group finish (ray costs vary widely per tile).
-// queue[0] is the next tile, queue[1] counts waves that found the queue
-// empty; the last of them resets both, so every launch starts from zero.
+// from the per-XCD queues until the image is done, so that no wave idles
+// while the slower waves of its work-group finish (ray costs vary widely per
+// tile).  Waves that find every queue dry count themselves out; the last one
+// clears the queues, so every launch starts from zero.
 __global__ __launch_bounds__(kBlock) void trace_kernel(TraceParams p) {
   __shared__ uint32_t stk[kStackLevels][kBlock];
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   constexpr uint32_t tw = kViewTileW, th = 64 / kViewTileW;
+  const uint32_t home = blockIdx.x % kQueues;
+  uint32_t qi = 0;
   for (;;) {
-    uint32_t t = 0;
-    if (lane == 0) t = atomicAdd(&p.queue[0], 1u);
-    t = __shfl(t, 0);
-    if (t >= p.total_tiles) {
-      if (lane == 0 && atomicAdd(&p.queue[1], 1u) == gridDim.x * (kBlock / 64) - 1) {
-        atomicExch(&p.queue[0], 0u);
-        atomicExch(&p.queue[1], 0u);
+    uint32_t t = 0, t_end = 0;
+    if (!take_tiles(p.queue, p.total_tiles, 1u, home, lane, qi, t, t_end)) {
+      if (lane == 0 && atomicAdd(&p.queue[kQueues * kQueueStride], 1u) == gridDim.x * (kBlock / 64) - 1) {
+        for (uint32_t i = 0; i <= kQueues; i++) atomicExch(&p.queue[i * kQueueStride], 0u);
       }
       break;
     }
@@ -611,8 +631,8 @@ int launch_beam(const BeamParams& p, void* stream) {
 // view from one work queue, so small views fill the machine as well as large
 // ones.  All per-batch values come from device memory (BatchHeader and
 // BatchView), so the three launches are captured once as a graph.
-__global__ void batch_reset_kernel(BatchHeader* hdr) {
-  if (threadIdx.x == 0) hdr->next_tile = 0;
+__global__ void batch_reset_kernel(uint32_t* queue) {
+  if (threadIdx.x < kQueues) queue[threadIdx.x * kQueueStride] = 0;
 }
 
 __global__ void batch_stage_kernel(BatchParams p) {
@@ -641,13 +661,12 @@ __global__ __launch_bounds__(kBlock) void batch_trace_kernel(BatchParams p) {
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t total = p.hdr->total_tiles, nviews = p.hdr->nviews;
   const uint32_t claim = p.hdr->claim, tw = p.hdr->tile_w, th = 64 / tw, beam = p.hdr->beam;
+  const uint32_t home = blockIdx.x % kQueues;
+  uint32_t qi = 0;
   for (;;) {
     // one queue access per wave: lane 0 claims, the wave shares the index
-    uint32_t t0 = 0;
-    if (lane == 0) t0 = atomicAdd(&p.hdr->next_tile, claim);
-    t0 = __shfl(t0, 0);
-    if (t0 >= total) break;
-    const uint32_t t1 = t0 + claim < total ? t0 + claim : total;
+    uint32_t t0 = 0, t1 = 0;
+    if (!take_tiles(p.queue, total, claim, home, lane, qi, t0, t1)) break;
     for (uint32_t t = t0; t < t1; t++) {
       uint32_t lo = 0, hi = nviews;  // view holding global tile t
       while (hi - lo > 1) {
@@ -724,7 +743,7 @@ __global__ __launch_bounds__(kBeamBlock) void batch_beam_kernel(BatchParams p) {
 
 int launch_batch(const BatchParams& p, uint32_t trace_blocks, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, p.hdr);
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, p.queue);
   hipLaunchKernelGGL(batch_stage_kernel, dim3((p.nchunks + 63) / 64, p.max_views), dim3(64), 0, s, p);
   hipLaunchKernelGGL(batch_beam_kernel, dim3(trace_blocks), dim3(kBeamBlock), 0, s, p);
   hipLaunchKernelGGL(batch_trace_kernel, dim3(trace_blocks), dim3(kBlock), 0, s, p);

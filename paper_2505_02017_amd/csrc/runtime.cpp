@@ -139,7 +139,7 @@ extern "C" int svd_world_create(const svd_world_desc* desc, void* pool_dev, size
   const uint64_t n = (uint64_t)desc->grid[0] * desc->grid[1] * desc->grid[2];
   const size_t desc_bytes = (size_t)n * 4 * sizeof(DevDag);
   const size_t view_bytes = ((size_t)n * 4 + 255) / 256 * 256;
-  const size_t ctl_bytes = 256;
+  const size_t ctl_bytes = kQueueBlockBytes;
   if (pool_bytes < desc_bytes + view_bytes + ctl_bytes)
     return svd_fail(SVD_ENOMEM, "world: pool smaller than its tables");
   uint32_t per_cu = 0;
@@ -546,6 +546,7 @@ static int batch_capture(svd_batch* b) {
   p.nchunks = w->nchunks;
   p.desc = w->d_desc;
   p.view_tables = b->d_tables;
+  p.queue = b->d_queue;
   if (b->exec) {
     hipGraphExecDestroy(b->exec);
     b->exec = nullptr;
@@ -590,15 +591,16 @@ extern "C" int svd_batch_create(svd_world* w, uint32_t max_views, svd_batch** ou
   b->max_views = max_views;
   const size_t views_bytes = (size_t)max_views * sizeof(BatchView);
   const size_t tables_bytes = ((size_t)max_views * w->nchunks * 4 + 255) / 256 * 256;
-  b->bytes = 256 + views_bytes + tables_bytes;
+  b->bytes = kQueueBlockBytes + 256 + views_bytes + tables_bytes;
   if (!w->alloc(b->bytes, &b->off)) {
     b->bytes = 0;
     batch_release(b);
     return svd_fail(SVD_ENOMEM, "batch: pool has no room for %u views", max_views);
   }
-  b->d_hdr = (BatchHeader*)(w->pool + b->off);
-  b->d_views = (BatchView*)(w->pool + b->off + 256);
-  b->d_tables = (uint32_t*)(w->pool + b->off + 256 + views_bytes);
+  b->d_queue = (uint32_t*)(w->pool + b->off);
+  b->d_hdr = (BatchHeader*)(w->pool + b->off + kQueueBlockBytes);
+  b->d_views = (BatchView*)(w->pool + b->off + kQueueBlockBytes + 256);
+  b->d_tables = (uint32_t*)(w->pool + b->off + kQueueBlockBytes + 256 + views_bytes);
   b->stage_bytes = 256 + views_bytes;
   hipError_t e = hipHostMalloc((void**)&b->h_stage, b->stage_bytes, hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);

@@ -75,13 +75,24 @@ struct TraceParams {
   uint32_t chunk_log2;
   uint32_t tiles_x;       // 16x4-pixel wave tiles per image row
   uint32_t total_tiles;
-  uint32_t* queue;        // [next tile, waves done]; both zero between launches
+  uint32_t* queue;        // tile queues (see kQueues); all zero between launches
   const uint32_t* view;   // per-chunk view entry
   const DevDag* desc;     // [chunk * 4 + lod]
   svd_hit* out;
   uint32_t beam;          // 1: each tile's first record holds its start bound
 };
 constexpr uint32_t kViewTileW = 16;  // per-view wave tile: 16 x 4 pixels
+
+// Tile queues of the persistent traces: one per XCD (a block's home queue is
+// blockIdx % kQueues, which follows the round-robin placement of blocks on
+// XCDs), each over a contiguous band of the tiles, so that the counters'
+// atomics stay in separate cache lines and a band's rays share one L2.  A
+// wave whose queue runs dry takes tiles from the next queues.  Counter q is
+// word q * kQueueStride of the queue block; word kQueues * kQueueStride
+// counts finished waves (per-view trace).
+constexpr uint32_t kQueues = 8;
+constexpr uint32_t kQueueStride = 32;  // u32 words: one 128-byte line per counter
+constexpr size_t kQueueBlockBytes = 2048;
 
 // Start bound of a tile, written by the beam pass into the first word of the
 // tile's first record (the trace reads it before writing the tile): whole
@@ -131,7 +142,7 @@ static_assert(sizeof(BatchView) == 256, "BatchView must stay 256 bytes");
 struct alignas(64) BatchHeader {
   uint32_t nviews;
   uint32_t total_tiles;
-  uint32_t next_tile;     // work-queue head (reset by a kernel, not a memset)
+  uint32_t unused;
   uint32_t tile_w;        // tile width in pixels (tile = tile_w x 64/tile_w)
   uint32_t claim;         // tiles a wave takes per queue access
   uint32_t beam;          // 1: run the beam pass (tile start bounds)
@@ -150,6 +161,7 @@ struct BatchParams {
   uint32_t nchunks;
   const DevDag* desc;
   uint32_t* view_tables;  // [view * nchunks + chunk]
+  uint32_t* queue;        // tile queues (kQueueBlockBytes), cleared by a kernel at each launch
 };
 
 // runtime.cpp: inward normals of the view cone's side planes (false = degenerate)
@@ -179,11 +191,10 @@ struct svd_blob {
 // Thread-local error message; returns `code` for convenient `return fail(...)`.
 int svd_fail(int code, const char* fmt, ...);
 
-// Default persistent grid of the per-view trace.  Fewer resident waves than
-// fit a CU trace 1440p views faster (blocks per CU 6 / 5 / 4 / 3: 3.87 /
-// 4.07 / 4.21 / 4.16 Grays/s on the 16x16-chunk map; contention of more
-// resident rays for the CU's cache is the likely cause).
-constexpr uint32_t kViewBlocksPerCu = 4;
+// Default persistent grid of the per-view trace: 6 blocks per CU (the most
+// that fit).  With per-XCD tile queues, 1440p views of the 16x16-chunk map
+// take 0.716 / 0.718 / 0.736 / 0.818 ms at 6 / 5 / 4 / 3 blocks per CU.
+constexpr uint32_t kViewBlocksPerCu = 6;
 
 // A world: the device descriptor table, the per-view table and queue, and a
 // first-fit sub-allocator over the rest of the caller's pool.  Residency is
@@ -265,13 +276,14 @@ int world_upload_lods(svd_world* w, uint32_t ci, const svd_blob* b, uint32_t mas
 int world_evict_lods(svd_world* w, uint32_t ci, uint32_t mask, hipStream_t stream);
 
 // A batch: device memory from the world's pool,
-//   [BatchHeader 64 B | pad to 256][BatchView x max_views][view tables: max_views x nchunks u32],
+//   [tile queues 2048 B][BatchHeader 64 B | pad to 256][BatchView x max_views][view tables: max_views x nchunks u32],
 // pinned host staging (header + views) guarded by an event, and the captured
 // graph (reset + stage + persistent trace) that every launch replays.
 struct svd_batch {
   svd_world* w = nullptr;
   uint32_t max_views = 0;
   size_t off = 0, bytes = 0;
+  uint32_t* d_queue = nullptr;
   svd::BatchHeader* d_hdr = nullptr;
   svd::BatchView* d_views = nullptr;
   uint32_t* d_tables = nullptr;

@@ -259,12 +259,12 @@ def make_desc(chunk_log2: int, grid, lod_count: int, thresholds=(256, 1024, 4096
 
 def table_bytes(grid) -> int:
     n = int(grid[0]) * int(grid[1]) * int(grid[2])
-    return n * 4 * 64 + (n * 4 + 255) // 256 * 256 + 256
+    return n * 4 * 64 + (n * 4 + 255) // 256 * 256 + 2048
 
 
 def batch_bytes(nchunks: int, max_views: int) -> int:
     """Pool bytes a batch of max_views views takes (see svd_batch_create)."""
-    return 256 + 256 * max_views + (max_views * nchunks * 4 + 255) // 256 * 256
+    return 2048 + 256 + 256 * max_views + (max_views * nchunks * 4 + 255) // 256 * 256
 
 
 class World:

@@ -179,7 +179,9 @@ def test_server_results_equal_alone(env, world, mode, views, inflight, tight, sf
         assert st["prefetches"] == 0
     if total > budget:
         assert st["evictions"] > 0
-    assert st["pool_used"] <= budget
+    n = sw.grid[0] * sw.grid[1] * sw.grid[2]
+    spare = 0 if mode == 0 else inflight * svdag.batch_bytes(n, views)  # plain mode makes no batch areas
+    assert st["pool_used"] <= budget + spare
     if mode == 0:
         assert st["launches"] <= len(cams)
 
