@@ -456,14 +456,27 @@ int launch_trace(const TraceParams& p, uint32_t blocks, void* stream) {
 // cells before that time, and starting its walk there (same exact instant
 // arithmetic as the world entry) changes no record.
 //
-// The cone test is conservative in FP64: its side planes n_i = C_i x C_(i+1)
-// are exact in i64 (|C| < 2^31) and rounded once to FP64 (error <= 2^10 per
-// component); box offsets are exact (< 2^34); the three products and two
-// sums then err by less than 2^47, so a cube is dropped only when its
-// farthest corner along n_i scores below -2^49.
+// The cone test runs in FP32 with a margin that covers its rounding.  Side
+// plane i has the exact i64 normal m_i = C_i x C_(i+1) (|C| < 2^31), scaled
+// by a power of two so that its largest component lies in [1/2, 1), then
+// rounded to FP32 (relative error <= 2^-24).  For a cube [lo, lo + s]
+// (integer voxels in [0, 2^15], s <= 2^10) the largest value of n_i . (x - o)
+// over it is
+//   n_i . lo + s P_i - n_i . o,    P_i = sum of the positive components,
+// evaluated with FMAs from the FP32 camera position o (in (-2^15, 2^16), so
+// rounded by at most 2^-8 per axis).  Every partial sum stays below 2^18, so
+// the four FMAs of the test err by at most 4 2^-6, the three of n_i . o by
+// 9 2^-8, the normal's rounding by 3 2^-24 2^17 and the camera's by 3 2^-8:
+// less than 0.14 together.  A cube is dropped
+// only when that value is below -1.  Distances are integer: with of / oc the
+// camera position rounded down / up to whole voxels, a cube is at least
+// max(lo - oc, of - (lo + s), 0) voxels away on each axis.
 struct BeamCone {
-  double n[4][3];
-  uint32_t mm;  // near-first octant order: bit a set when the tile looks down axis a
+  float n[4][3];
+  float pos[4];  // sum of the positive components of n_i
+  float c[4];    // n_i . o
+  int32_t of[3], oc[3];
+  uint32_t mm;   // near-first octant order: bit a set when the tile looks down axis a
 };
 
 __host__ __device__ inline bool beam_cone(const BeamParams& p, uint32_t x0, uint32_t y0, uint32_t x1, uint32_t y1,
@@ -473,8 +486,13 @@ __host__ __device__ inline bool beam_cone(const BeamParams& p, uint32_t x0, uint
   _Pragma("unroll") for (int i = 0; i < 4; i++)
     _Pragma("unroll") for (int a = 0; a < 3; a++) C[i][a] = p.A[a] + (int64_t)px[i] * p.BX[a] + (int64_t)py[i] * p.BY[a];
   q.mm = 0;
-  _Pragma("unroll") for (int a = 0; a < 3; a++)
+  float o[3];
+  _Pragma("unroll") for (int a = 0; a < 3; a++) {
     if (C[0][a] + C[2][a] < 0) q.mm |= 1u << a;
+    o[a] = (float)((double)p.O[a] * (1.0 / 65536.0));
+    q.of[a] = (int32_t)(p.O[a] >> 16);
+    q.oc[a] = (int32_t)(-((-p.O[a]) >> 16));
+  }
   _Pragma("unroll") for (int i = 0; i < 4; i++) {
     const int64_t* u = C[i];
     const int64_t* v = C[(i + 1) & 3];
@@ -484,122 +502,165 @@ __host__ __device__ inline bool beam_cone(const BeamParams& p, uint32_t x0, uint
       s0 += (__int128)m[a] * C[(i + 2) & 3][a];
       s1 += (__int128)m[a] * C[(i + 3) & 3][a];
     }
-    double sg;
-    if (s0 >= 0 && s1 >= 0 && (s0 > 0 || s1 > 0)) sg = 1.0;
-    else if (s0 <= 0 && s1 <= 0 && (s0 < 0 || s1 < 0)) sg = -1.0;
+    int sg;
+    if (s0 >= 0 && s1 >= 0 && (s0 > 0 || s1 > 0)) sg = 1;
+    else if (s0 <= 0 && s1 <= 0 && (s0 < 0 || s1 < 0)) sg = -1;
     else return false;  // degenerate cone (a one-pixel row or column)
-    _Pragma("unroll") for (int a = 0; a < 3; a++) q.n[i][a] = sg * (double)m[a];
+    uint64_t big = 0;
+    _Pragma("unroll") for (int a = 0; a < 3; a++) {
+      const uint64_t am = m[a] < 0 ? (uint64_t)0 - (uint64_t)m[a] : (uint64_t)m[a];
+      big = am > big ? am : big;
+    }
+    int e = 0;  // 2^e > big >= 2^(e-1): scale so the largest component is in [1/2, 1)
+    while (e < 64 && (big >> e)) e++;
+    q.pos[i] = 0.0f;
+    q.c[i] = 0.0f;
+    _Pragma("unroll") for (int a = 0; a < 3; a++) {
+      q.n[i][a] = (float)sg * (float)ldexp((double)m[a], -e);
+      q.pos[i] += q.n[i][a] > 0.0f ? q.n[i][a] : 0.0f;
+      q.c[i] = fmaf(q.n[i][a], o[a], q.c[i]);
+    }
   }
   return true;
 }
 
-// Closed cube [lo, lo + size] (voxels) entirely outside the cone?
-__host__ __device__ __forceinline__ bool beam_outside(const BeamCone& q, const int64_t O[3], const int64_t lo[3],
-                                                      int64_t size) {
+// Closed cube [lo, lo + s] (voxels) entirely outside the cone?
+__host__ __device__ __forceinline__ bool beam_outside(const BeamCone& q, const int32_t lo[3], int32_t s) {
+  const float l0 = (float)lo[0], l1 = (float)lo[1], l2 = (float)lo[2], fs = (float)s;
   bool out = false;
   _Pragma("unroll") for (int i = 0; i < 4; i++) {
-    double sdot = 0.0;
-    _Pragma("unroll") for (int a = 0; a < 3; a++) {
-      const int64_t x = ((q.n[i][a] >= 0.0 ? lo[a] + size : lo[a]) << 16) - O[a];
-      sdot = sdot + q.n[i][a] * (double)x;
-    }
-    out |= sdot < -0x1p49;
+    const float v = fmaf(q.n[i][0], l0, fmaf(q.n[i][1], l1, fmaf(q.n[i][2], l2, fmaf(fs, q.pos[i], -q.c[i]))));
+    out |= v < -1.0f;
   }
   return out;
 }
 
-// Chebyshev distance from O to the closed box [lo, hi] (voxels), in whole
-// voxels rounded down, at most 65535.
-__host__ __device__ __forceinline__ uint32_t beam_dist(const int64_t O[3], const int64_t lo[3], const int64_t hi[3]) {
-  int64_t d = 0;
+// Chebyshev distance from the camera to the closed cube [lo, lo + s], in
+// whole voxels rounded down, at most 65535.
+__host__ __device__ __forceinline__ uint32_t beam_dist(const BeamCone& q, const int32_t lo[3], int32_t s) {
+  int32_t d = 0;
   _Pragma("unroll") for (int a = 0; a < 3; a++) {
-    const int64_t l = lo[a] << 16, h = hi[a] << 16;
-    const int64_t e = O[a] < l ? l - O[a] : (O[a] > h ? O[a] - h : 0);
-    d = e > d ? e : d;
+    const int32_t e0 = lo[a] - q.oc[a], e1 = q.of[a] - (lo[a] + s);
+    d = e0 > d ? e0 : d;
+    d = e1 > d ? e1 : d;
   }
-  d >>= 16;
   return (uint32_t)(d < 65535 ? d : 65535);
 }
 
-// Start bound of the tile with pixel corners (x0, y0)..(x1, y1).  `stk` holds
-// the DFS path (two words per node level, element stride `ss`).
+// Children mask with bit i standing for octant i ^ mm: the near-first order.
+__host__ __device__ __forceinline__ uint32_t beam_order(uint32_t m, uint32_t mm) {
+  if (mm & 1u) m = ((m & 0x55u) << 1) | ((m >> 1) & 0x55u);
+  if (mm & 2u) m = ((m & 0x33u) << 2) | ((m >> 2) & 0x33u);
+  if (mm & 4u) m = ((m & 0x0Fu) << 4) | ((m >> 4) & 0x0Fu);
+  return m;
+}
+
+// Start bound of the tile with pixel corners (x0, y0)..(x1, y1).  Chunks are
+// visited shell by shell around the camera's chunk, and inside each a
+// depth-first walk of the DAG takes the near octants first; both are cut by
+// the bound found so far.  One loop drives the shell walk and the DAG walk,
+// so lanes of a wave at different stages of their tiles never wait on each
+// other's inner loops.  `stk` holds the DAG path (two words per node level,
+// element stride `ss`).
 __host__ __device__ inline uint32_t beam_tile(const BeamParams& p, uint32_t x0, uint32_t y0, uint32_t x1, uint32_t y1,
                                               uint32_t* stk, uint32_t ss) {
   BeamCone q;
   if (!beam_cone(p, x0, y0, x1, y1, q)) return 0u;
   const int CL = (int)p.chunk_log2;
-  const int64_t S = (int64_t)1 << CL;
-  int64_t c0[3], rmin = 0, rmax = 0;
+  const int32_t S = (int32_t)1 << CL;
+  const int32_t g[3] = {(int32_t)p.grid[0], (int32_t)p.grid[1], (int32_t)p.grid[2]};
+  int32_t c0[3], rmin = 0, rmax = 0;
   _Pragma("unroll") for (int a = 0; a < 3; a++) {
-    c0[a] = (p.O[a] >> 16) >> CL;  // chunk of the camera (floor), maybe outside the grid
-    const int64_t g = (int64_t)p.grid[a];
-    const int64_t in = c0[a] < 0 ? -c0[a] : (c0[a] >= g ? c0[a] - g + 1 : 0);
-    const int64_t out = c0[a] < 0 ? g - 1 - c0[a] : (c0[a] >= g ? c0[a] : (c0[a] > g - 1 - c0[a] ? c0[a] : g - 1 - c0[a]));
+    c0[a] = q.of[a] >> CL;  // chunk of the camera (floor), maybe outside the grid
+    const int32_t in = c0[a] < 0 ? -c0[a] : (c0[a] >= g[a] ? c0[a] - g[a] + 1 : 0);
+    const int32_t out = c0[a] < 0 ? g[a] - 1 - c0[a] : (c0[a] >= g[a] ? c0[a] : (c0[a] > g[a] - 1 - c0[a] ? c0[a] : g[a] - 1 - c0[a]));
     rmin = in > rmin ? in : rmin;
     rmax = out > rmax ? out : rmax;
   }
+  // Shell cursor: shell r (every axis range clipped to the grid is non-empty
+  // from rmin on), row (y, z) in the clipped ranges, x across the row: every
+  // cell on the shell's top and bottom faces and side rows, only the two ends
+  // on the other rows.
+  int32_t r = rmin;
+  int32_t z = c0[2] - r < 0 ? 0 : c0[2] - r;
+  int32_t y = c0[1] - r < 0 ? 0 : c0[1] - r;
+  int32_t x = c0[0] - r;
   uint32_t best = kBeamNone;
-  for (int64_t r = rmin; r <= rmax; r++) {
-    // every chunk of ring r is at least (r - 1) chunks away on some axis
-    if (r >= 1 && best != kBeamNone && (uint64_t)((r - 1) * S) >= best) break;
-    const int64_t zl = c0[2] - r < 0 ? 0 : c0[2] - r, zh = c0[2] + r >= p.grid[2] ? p.grid[2] - 1 : c0[2] + r;
-    const int64_t yl = c0[1] - r < 0 ? 0 : c0[1] - r, yh = c0[1] + r >= p.grid[1] ? p.grid[1] - 1 : c0[1] + r;
-    for (int64_t z = zl; z <= zh; z++) {
-      for (int64_t y = yl; y <= yh; y++) {
-        const bool face = z == c0[2] - r || z == c0[2] + r || y == c0[1] - r || y == c0[1] + r;
-        const int64_t step = face || r == 0 ? 1 : 2 * r;
-        for (int64_t x = c0[0] - r; x <= c0[0] + r; x += step) {
-          if (x < 0 || x >= (int64_t)p.grid[0]) continue;
-          const uint32_t ci = (uint32_t)(x + p.grid[0] * (y + p.grid[1] * z));
-          const uint32_t v = p.view[ci];
-          if (v & (kViewCulled | kViewEmpty)) continue;
-          const int k = (int)(v & kViewLodMask);
-          const int64_t base[3] = {x * S, y * S, z * S};
-          if (v & kViewMissing) {  // rays must reach it to report it
-            const int64_t hi[3] = {base[0] + S, base[1] + S, base[2] + S};
-            const uint32_t d = beam_dist(p.O, base, hi);
-            if (d < best && !beam_outside(q, p.O, base, S)) best = d;
-            continue;
-          }
-          const DevDag* dag = &p.desc[(size_t)ci * 4 + k];
-          // depth-first over the DAG, nearest octants first, cut by the bound so far
-          const gptr32 nodes = (gptr32)dag->nodes;
-          int L = CL;
-          uint32_t wd = dag->root, it = 0;
-          int64_t org[3] = {base[0], base[1], base[2]};
-          for (;;) {
-            if (it == 8) {
-              if (L == CL) break;
-              L++;
-              wd = stk[(2 * (L - 3)) * ss];
-              it = stk[(2 * (L - 3) + 1) * ss];
-              _Pragma("unroll") for (int a = 0; a < 3; a++) org[a] = base[a] + ((org[a] - base[a]) & ~(((int64_t)1 << L) - 1));
-              continue;
-            }
-            const uint32_t o = it ^ q.mm;
-            it++;
-            if (!((wd >> (kPtrBits + o)) & 1u)) continue;
-            const int64_t half = (int64_t)1 << (L - 1);
-            const int64_t lo[3] = {org[0] + ((o & 1) ? half : 0), org[1] + ((o & 2) ? half : 0),
-                                   org[2] + ((o & 4) ? half : 0)};
-            const int64_t hi[3] = {lo[0] + half, lo[1] + half, lo[2] + half};
-            const uint32_t d = beam_dist(p.O, lo, hi);
-            if (d >= best || beam_outside(q, p.O, lo, half)) continue;
-            if (L - 1 == k + 1) {  // a 2^3 sub-block of a leaf: as fine as the bound goes
-              best = d;
-              continue;
-            }
-            const uint32_t cw = nodes[(wd & kPtrMask) + __builtin_popcount((wd >> kPtrBits) & ((1u << o) - 1u))];
-            stk[(2 * (L - 3)) * ss] = wd;
-            stk[(2 * (L - 3) + 1) * ss] = it;
-            L--;
-            wd = cw;
-            it = 0;
-            _Pragma("unroll") for (int a = 0; a < 3; a++) org[a] = lo[a];
+  int L = 0;  // level of the DAG node being walked; 0 between chunks
+  int k = 0;
+  uint32_t wd = 0, rem = 0;
+  int32_t org[3] = {0, 0, 0};
+  gptr32 nodes = nullptr;
+  for (;;) {
+    if (L == 0) {
+      // every chunk of shell r is at least (r - 1) chunks away on some axis
+      if (r > rmax || (r >= 1 && best != kBeamNone && (uint32_t)((r - 1) * S) >= best)) break;
+      const int32_t cx = x, cy = y, cz = z;
+      const bool face = r == 0 || z == c0[2] - r || z == c0[2] + r || y == c0[1] - r || y == c0[1] + r;
+      x += face ? 1 : 2 * r;
+      if (x > c0[0] + r) {
+        x = c0[0] - r;
+        const int32_t yh = c0[1] + r >= g[1] ? g[1] - 1 : c0[1] + r;
+        if (++y > yh) {
+          y = c0[1] - r < 0 ? 0 : c0[1] - r;
+          const int32_t zh = c0[2] + r >= g[2] ? g[2] - 1 : c0[2] + r;
+          if (++z > zh) {
+            r++;
+            z = c0[2] - r < 0 ? 0 : c0[2] - r;
+            y = c0[1] - r < 0 ? 0 : c0[1] - r;
+            x = c0[0] - r;
           }
         }
       }
+      if (cx < 0 || cx >= g[0]) continue;
+      const uint32_t ci = (uint32_t)cx + p.grid[0] * ((uint32_t)cy + p.grid[1] * (uint32_t)cz);
+      const uint32_t v = p.view[ci];
+      if (v & (kViewCulled | kViewEmpty)) continue;
+      k = (int)(v & kViewLodMask);
+      org[0] = cx * S;
+      org[1] = cy * S;
+      org[2] = cz * S;
+      if (v & kViewMissing) {  // rays must reach it to report it
+        const uint32_t d = beam_dist(q, org, S);
+        if (d < best && !beam_outside(q, org, S)) best = d;
+        continue;
+      }
+      const DevDag* dag = &p.desc[(size_t)ci * 4 + k];
+      nodes = (gptr32)dag->nodes;
+      wd = dag->root;
+      rem = beam_order(wd >> kPtrBits, q.mm);
+      L = CL;
+      continue;
     }
+    if (rem == 0) {  // node done: back to its parent
+      if (L == CL) {
+        L = 0;
+        continue;
+      }
+      L++;
+      wd = stk[(2 * (L - 3)) * ss];
+      rem = stk[(2 * (L - 3) + 1) * ss];
+      _Pragma("unroll") for (int a = 0; a < 3; a++) org[a] &= ~((1 << L) - 1);
+      continue;
+    }
+    const uint32_t o = (uint32_t)__builtin_ctz(rem) ^ q.mm;
+    rem &= rem - 1u;
+    const int32_t half = 1 << (L - 1);
+    const int32_t lo[3] = {org[0] + ((o & 1) ? half : 0), org[1] + ((o & 2) ? half : 0),
+                           org[2] + ((o & 4) ? half : 0)};
+    const uint32_t d = beam_dist(q, lo, half);
+    if (d >= best || beam_outside(q, lo, half)) continue;
+    if (L - 1 == k + 1) {  // a 2^3 sub-block of a leaf: as fine as the bound goes
+      best = d;
+      continue;
+    }
+    const uint32_t cw = nodes[(wd & kPtrMask) + __builtin_popcount((wd >> kPtrBits) & ((1u << o) - 1u))];
+    stk[(2 * (L - 3)) * ss] = wd;
+    stk[(2 * (L - 3) + 1) * ss] = rem;
+    L--;
+    wd = cw;
+    rem = beam_order(cw >> kPtrBits, q.mm);
+    _Pragma("unroll") for (int a = 0; a < 3; a++) org[a] = lo[a];
   }
   return best;
 }
