@@ -162,6 +162,33 @@ struct Ray {
   }
 };
 
+// Leave cell c (any level; E its exit-plane numerators): the earliest exit
+// plane sets the ray's new instant and c steps to the neighbour across it (on
+// every axis that ties).  `diff` gets the changed coordinate bits.  False when
+// D == 0: the ray never leaves the cell.
+__host__ __device__ __forceinline__ bool exit_cell(Ray& r, const uint32_t E[3], int32_t c[3], uint32_t& diff) {
+  // Key of axis a, scaled against axis b: E_a * 2|D_b| + class_a.
+  uint32_t bE = E[0], bA2 = r.ad2[0], bC = r.cls(0), sm = 1u;
+  _Pragma("unroll") for (int a = 1; a < 3; a++) {
+    const uint64_t ka = (uint64_t)E[a] * bA2 + r.cls(a);
+    const uint64_t kb = (uint64_t)bE * r.ad2[a] + bC;
+    const bool lt = ka < kb, eq = ka == kb;
+    bE = lt ? E[a] : bE;
+    bA2 = lt ? r.ad2[a] : bA2;
+    bC = lt ? r.cls(a) : bC;
+    sm = lt ? (1u << a) : (eq ? sm | (1u << a) : sm);
+  }
+  if (bA2 == 0) return false;
+  r.set_time(bE, bA2 >> 1, bC);  // |D| of the exit axis (2|D| < 2^32 is exact)
+  diff = 0;
+  _Pragma("unroll") for (int a = 0; a < 3; a++) {
+    const uint32_t s = (sm >> a) & 1u;
+    diff |= (uint32_t)(c[a] ^ (c[a] + (int32_t)s));
+    c[a] += (int32_t)s;
+  }
+  return true;
+}
+
 // The whole per-pixel path: ray setup, world entry, chunk walk, DAG
 // traversal, hit resolve.  `stk` is this ray's node-word stack (levels 3..10,
 // element stride `ss`).
@@ -221,114 +248,101 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
   }
 
   int lev = CL, k = 0;
-  bool at_chunk = true;
   uint32_t mask = 0, lmask = 0, ptr = 0, ci = 0, iter = 0;
   uint64_t bitmap = 0;
   gptr32 nodes = nullptr;
   gptr64 leaves = nullptr;
+  // Chunk walk: c and E describe the current chunk (level CL).
   while (status == kRunning) {
     if (++iter > kMaxIter) { status = kFault; break; }
-    bool step = false;
-    if (at_chunk) {
-      if (c[0] >= (int32_t)p.grid[0] || c[1] >= (int32_t)p.grid[1] || c[2] >= (int32_t)p.grid[2]) {
-        status = kMiss;  // left the world
-        break;
-      }
-      uint32_t co[3];
-      _Pragma("unroll") for (int a = 0; a < 3; a++) co[a] = r.cls(a) ? p.grid[a] - 1 - (uint32_t)c[a] : (uint32_t)c[a];
-      ci = co[0] + p.grid[0] * (co[1] + p.grid[1] * co[2]);
-      const uint32_t v = p.view[ci];
-      if (v & (kViewCulled | kViewEmpty)) {
-        step = true;
-      } else if (v & kViewMissing) {
+    if (c[0] >= (int32_t)p.grid[0] || c[1] >= (int32_t)p.grid[1] || c[2] >= (int32_t)p.grid[2]) {
+      status = kMiss;  // left the world
+      break;
+    }
+    uint32_t co[3];
+    _Pragma("unroll") for (int a = 0; a < 3; a++) co[a] = r.cls(a) ? p.grid[a] - 1 - (uint32_t)c[a] : (uint32_t)c[a];
+    ci = co[0] + p.grid[0] * (co[1] + p.grid[1] * co[2]);
+    const uint32_t v = p.view[ci];
+    if (!(v & (kViewCulled | kViewEmpty))) {
+      if (v & kViewMissing) {
         status = kNotLoaded;
         break;
-      } else {
-        k = (int)(v & kViewLodMask);
-        const DevDag* dag = &p.desc[(size_t)ci * 4 + k];
-        nodes = (gptr32)dag->nodes;
-        leaves = (gptr64)dag->leaves;
-        const uint32_t root = dag->root;
-        stk[(CL - 3) * ss] = root;
-        mask = root >> kPtrBits;
-        ptr = 0;
-        at_chunk = false;
       }
-    }
-    if (!step) {
-      // descend: the child of cell c (level lev) holding the current instant
-      const uint32_t half = 1u << (lev - 1 + 16);
-      uint32_t bits = 0;
-      _Pragma("unroll") for (int a = 0; a < 3; a++) {
-        const uint32_t nm = E[a] - half;  // mid-plane numerator
-        const uint32_t b = (uint32_t)(E[a] < half) | (uint32_t)r.past_n(a, nm);
-        c[a] = 2 * c[a] + (int32_t)b;
-        E[a] = b ? E[a] : nm;
-        bits |= b << a;
-      }
-      lev--;
-      const uint32_t oct = bits ^ r.mm;  // octant in the unmirrored node
-      if ((mask >> oct) & 1u) {
-        if (lev == k) { status = kHit; break; }
-        if (lev >= k + 2) {
-          const uint32_t w = nodes[ptr + __builtin_popcount(mask & ((1u << oct) - 1u))];
+      k = (int)(v & kViewLodMask);
+      const DevDag* dag = &p.desc[(size_t)ci * 4 + k];
+      nodes = (gptr32)dag->nodes;
+      leaves = (gptr64)dag->leaves;
+      const uint32_t root = dag->root;
+      stk[(CL - 3) * ss] = root;
+      mask = root >> kPtrBits;
+      ptr = 0;
+      // DAG walk inside the chunk, until a hit or the ray leaves the chunk
+      for (;;) {
+        // descend: the child of cell c (level lev) holding the current instant
+        const uint32_t half = 1u << (lev - 1 + 16);
+        uint32_t bits = 0;
+        _Pragma("unroll") for (int a = 0; a < 3; a++) {
+          const uint32_t nm = E[a] - half;  // mid-plane numerator
+          const uint32_t b = (uint32_t)(E[a] < half) | (uint32_t)r.past_n(a, nm);
+          c[a] = 2 * c[a] + (int32_t)b;
+          E[a] = b ? E[a] : nm;
+          bits |= b << a;
+        }
+        lev--;
+        const uint32_t oct = bits ^ r.mm;  // octant in the unmirrored node
+        if ((mask >> oct) & 1u) {
+          if (lev == k) { status = kHit; break; }
+          if (lev >= k + 2) {
+            const uint32_t w = nodes[ptr + __builtin_popcount(mask & ((1u << oct) - 1u))];
+            mask = w >> kPtrBits;
+            ptr = w & kPtrMask;
+            if (lev >= k + 3) {
+              stk[(lev - 3) * ss] = w;
+            } else {  // a leaf: its word carries the sub-block summary
+              lmask = mask;
+              bitmap = leaves[ptr];
+            }
+          } else {
+            mask = (uint32_t)(bitmap >> (8 * oct)) & 0xFFu;
+          }
+          continue;
+        }
+        if (++iter > kMaxIter) { status = kFault; break; }
+        // the child is empty: leave it through its earliest exit plane
+        uint32_t diff;
+        if (!exit_cell(r, E, c, diff)) { status = kMiss; break; }
+        const int pl = lev + (32 - __builtin_clz(diff));  // lowest common ancestor level
+        if (pl > CL) {  // into the next chunk
+          _Pragma("unroll") for (int a = 0; a < 3; a++) {
+            c[a] >>= (CL - lev);
+            E[a] = ((uint32_t)(c[a] + 1) << (CL + 16)) - r.Oml[a];
+          }
+          lev = CL;
+          break;
+        }
+        // exit planes of the ancestor cell (numerators in [0, 2^32) inside the world)
+        _Pragma("unroll") for (int a = 0; a < 3; a++) {
+          c[a] >>= (pl - lev);
+          E[a] = ((uint32_t)(c[a] + 1) << (pl + 16)) - r.Oml[a];
+        }
+        lev = pl;
+        if (lev >= k + 3) {
+          const uint32_t w = stk[(lev - 3) * ss];
           mask = w >> kPtrBits;
           ptr = w & kPtrMask;
-          if (lev >= k + 3) {
-            stk[(lev - 3) * ss] = w;
-          } else {  // a leaf: its word carries the sub-block summary
-            lmask = mask;
-            bitmap = leaves[ptr];
-          }
+        } else if (lev == k + 2) {
+          mask = lmask;
         } else {
-          mask = (uint32_t)(bitmap >> (8 * oct)) & 0xFFu;
+          const uint32_t o1 = (((uint32_t)c[0] & 1u) | (((uint32_t)c[1] & 1u) << 1) | (((uint32_t)c[2] & 1u) << 2)) ^ r.mm;
+          mask = (uint32_t)(bitmap >> (8 * o1)) & 0xFFu;
         }
-        continue;
       }
+      continue;
     }
-    // ---- step out of the empty cell c at level lev: earliest exit plane.
-    // Key of axis a, scaled against axis b: E_a * 2|D_b| + class_a.
-    uint32_t bE = E[0], bA = r.ad[0], bA2 = r.ad2[0], bC = r.cls(0), sm = 1u;
-    _Pragma("unroll") for (int a = 1; a < 3; a++) {
-      const uint64_t ka = (uint64_t)E[a] * bA2 + r.cls(a);
-      const uint64_t kb = (uint64_t)bE * r.ad2[a] + bC;
-      const bool lt = ka < kb, eq = ka == kb;
-      bE = lt ? E[a] : bE;
-      bA = lt ? r.ad[a] : bA;
-      bA2 = lt ? r.ad2[a] : bA2;
-      bC = lt ? r.cls(a) : bC;
-      sm = lt ? (1u << a) : (eq ? sm | (1u << a) : sm);
-    }
-    if (bA == 0) { status = kMiss; break; }  // D == 0: the ray never leaves this cell
-    r.set_time(bE, bA, bC);
-    uint32_t diff = 0;
-    _Pragma("unroll") for (int a = 0; a < 3; a++) {
-      const uint32_t s = (sm >> a) & 1u;
-      diff |= (uint32_t)(c[a] ^ (c[a] + (int32_t)s));
-      c[a] += (int32_t)s;
-    }
-    int pl = lev + (32 - __builtin_clz(diff));  // lowest common ancestor level
-    if (pl > CL) {
-      pl = CL;
-      at_chunk = true;
-    }
-    // exit planes of the ancestor cell (numerators in [0, 2^32) inside the world)
-    _Pragma("unroll") for (int a = 0; a < 3; a++) {
-      c[a] >>= (pl - lev);
-      E[a] = ((uint32_t)(c[a] + 1) << (pl + 16)) - r.Oml[a];
-    }
-    lev = pl;
-    if (at_chunk) continue;
-    if (lev >= k + 3) {
-      const uint32_t w = stk[(lev - 3) * ss];
-      mask = w >> kPtrBits;
-      ptr = w & kPtrMask;
-    } else if (lev == k + 2) {
-      mask = lmask;
-    } else {
-      const uint32_t o1 = (((uint32_t)c[0] & 1u) | (((uint32_t)c[1] & 1u) << 1) | (((uint32_t)c[2] & 1u) << 2)) ^ r.mm;
-      mask = (uint32_t)(bitmap >> (8 * o1)) & 0xFFu;
-    }
+    // an empty or culled chunk: cross it
+    uint32_t diff;
+    if (!exit_cell(r, E, c, diff)) { status = kMiss; break; }
+    _Pragma("unroll") for (int a = 0; a < 3; a++) E[a] = ((uint32_t)(c[a] + 1) << (CL + 16)) - r.Oml[a];
   }
 
   uint4 rec = make_uint4(0u, 0u, 0x7F800000u /* +inf */, 0xFFFFFFFFu);
@@ -806,7 +820,10 @@ int launch_batch(const BatchParams& p, uint32_t trace_blocks, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, p.queue);
   hipLaunchKernelGGL(batch_stage_kernel, dim3((p.nchunks + 63) / 64, p.max_views), dim3(64), 0, s, p);
-  hipLaunchKernelGGL(batch_beam_kernel, dim3(trace_blocks), dim3(kBeamBlock), 0, s, p);
+  // one-wave beam blocks, twice as many waves as the trace: the beam walk is
+  // latency-bound, and blocks past the last tile (or of a batch without the
+  // beam) exit at once
+  hipLaunchKernelGGL(batch_beam_kernel, dim3(trace_blocks * 8), dim3(kBeamBlock), 0, s, p);
   hipLaunchKernelGGL(batch_trace_kernel, dim3(trace_blocks), dim3(kBlock), 0, s, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return svd_fail(SVD_EDEVICE, "batch launch: %s", hipGetErrorString(e));
