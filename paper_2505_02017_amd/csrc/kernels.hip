@@ -307,8 +307,10 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
           }
           continue;
         }
-        if (++iter > kMaxIter) { status = kFault; break; }
-        // the child is empty: leave it through its earliest exit plane
+        // the child is empty: leave it through its earliest exit plane (no
+        // iteration guard here: each exit moves the cell forward on some axis
+        // of the mirrored ray and each descent lowers the level, so the walk
+        // inside a chunk ends whatever the DAG holds)
         uint32_t diff;
         if (!exit_cell(r, E, c, diff)) { status = kMiss; break; }
         const int pl = lev + (32 - __builtin_clz(diff));  // lowest common ancestor level
