@@ -238,9 +238,9 @@ int svd_trace_frame(svd_world* w, const svd_ray_frame* frame, svd_hit* out_dev, 
  *   resolve) over the view table of the last svd_view_stage, which must have
  *   been given an identical frame (else SVD_EINVAL); with SVD_BEAM staged,
  *   runs the beam pass first unless svd_view_beam did.
- * The beam pass is off by default: on MI355X it cuts the trace's
- * instructions about 2x but hardly its time (the surface iterations it
- * leaves are bound by dependent-load latency), and costs more than it saves. */
+ * The beam pass is off by default: on MI355X it cuts the trace's time by
+ * about a quarter, but its own search (one serial chain of dependent loads
+ * per tile) costs more than that. */
 int svd_view_stage(svd_world* w, const svd_ray_frame* frame, uint32_t flags, void* stream);
 int svd_view_beam(svd_world* w, const svd_ray_frame* frame, svd_hit* out_dev, void* stream);
 int svd_view_trace(svd_world* w, const svd_ray_frame* frame, svd_hit* out_dev, void* stream);
