@@ -406,7 +406,7 @@ __device__ __forceinline__ bool take_tiles(uint32_t* queue, uint32_t total, uint
     const uint32_t hi = (uint32_t)((uint64_t)total * (q + 1) / kQueues);
     uint32_t t = 0;
     if (lane == 0) t = atomicAdd(&queue[q * kQueueStride], claim);
-    t = __shfl(t, 0);
+    t = __builtin_amdgcn_readlane(t, 0);  // wave-uniform: the tile math and view lookup stay scalar
     if (t < hi - lo) {
       t0 = lo + t;
       t1 = t0 + claim < hi ? t0 + claim : hi;
@@ -733,7 +733,9 @@ __global__ void batch_stage_kernel(BatchParams p) {
   p.view_tables[(size_t)v * p.nchunks + ci] = stage_chunk(sp, ci);
 }
 
-__global__ __launch_bounds__(kBlock) void batch_trace_kernel(BatchParams p) {
+// Held to 80 VGPRs (6 blocks of 4 waves per CU), which it fits without
+// spilling; left alone the compiler takes 83 and only 5 blocks fit.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 6))) void batch_trace_kernel(BatchParams p) {
   __shared__ uint32_t stk[kStackLevels][kBlock];
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t total = p.hdr->total_tiles, nviews = p.hdr->nviews;

@@ -548,7 +548,7 @@ static int batch_capture(svd_batch* b) {
   p.view_tables = b->d_tables;
   p.queue = b->d_queue;
   if (b->exec) {
-    hipGraphExecDestroy(b->exec);
+    (void)hipGraphExecDestroy(b->exec);
     b->exec = nullptr;
   }
   hipGraph_t g = nullptr;
@@ -565,21 +565,23 @@ static int batch_capture(svd_batch* b) {
     e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
     if (e != hipSuccess) rc = svd_fail(SVD_EDEVICE, "batch graph: %s", hipGetErrorString(e));
   }
-  if (g) hipGraphDestroy(g);
+  if (g) (void)hipGraphDestroy(g);
   return rc;
 }
 
 static int batch_release(svd_batch* b) {
   if (!b) return SVD_OK;
-  if (b->launched && b->finished) hipEventSynchronize(b->finished);
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->cap) hipStreamDestroy(b->cap);
-  if (b->staged) hipEventDestroy(b->staged);
-  if (b->finished) hipEventDestroy(b->finished);
-  if (b->h_stage) hipHostFree(b->h_stage);
+  int rc = SVD_OK;
+  if (b->launched && b->finished && hipEventSynchronize(b->finished) != hipSuccess)
+    rc = svd_fail(SVD_EDEVICE, "batch destroy: waiting for the last launch failed");
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->staged) (void)hipEventDestroy(b->staged);
+  if (b->finished) (void)hipEventDestroy(b->finished);
+  if (b->h_stage) (void)hipHostFree(b->h_stage);
   if (b->w && b->bytes) b->w->release(b->off, b->bytes);
   delete b;
-  return SVD_OK;
+  return rc;
 }
 
 extern "C" int svd_batch_create(svd_world* w, uint32_t max_views, svd_batch** out) {
@@ -752,7 +754,7 @@ static int batch_time(svd_batch* b, const svd_camera* cams, uint32_t n, svd_hit*
     if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
       return svd_fail(SVD_EDEVICE, "tune: sync failed");
     float ms = 0;
-    hipEventElapsedTime(&ms, e0, e1);
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return svd_fail(SVD_EDEVICE, "tune: event timing failed");
     if (r > 0) t.push_back(ms);
   }
   std::sort(t.begin(), t.end());
@@ -769,7 +771,7 @@ extern "C" int svd_batch_tune(svd_batch* b, const svd_camera* cams, uint32_t n, 
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-    if (e0) hipEventDestroy(e0);
+    if (e0) (void)hipEventDestroy(e0);
     return svd_fail(SVD_EDEVICE, "tune: event create failed");
   }
   const uint32_t widths[] = {8, 16, 32};
@@ -797,8 +799,8 @@ extern "C" int svd_batch_tune(svd_batch* b, const svd_camera* cams, uint32_t n, 
     if (rc == SVD_OK) rc = batch_time(b, cams, n, out_dev, out_records, reps, s, e0, e1, &med);
     if (rc == SVD_OK && med < best) { best = med; bo = occ; }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   const int rc2 = svd_batch_set_occupancy(b, bo);
   if (rc == SVD_OK) rc = rc2;
   if (best_ms) *best_ms = best;

@@ -462,7 +462,20 @@ static bool stopping(svd_server* s) {
 }
 
 static void worker(svd_server* s) {
-  hipSetDevice(s->device);
+  if (hipSetDevice(s->device) != hipSuccess) {
+    // no device on this thread: every request fails until the server stops
+    for (;;) {
+      std::deque<Request> got;
+      {
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->wake.wait(lk, [s] { return s->stop || !s->inbox.empty(); });
+        got.swap(s->inbox);
+        if (got.empty() && s->stop) return;
+      }
+      for (const Request& r : got) finish(s, r, SVD_EDEVICE, 0, 0.0, s->now());
+      s->done_cv.notify_all();
+    }
+  }
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(s->mu);
@@ -488,12 +501,12 @@ static void worker(svd_server* s) {
 static void server_release(svd_server* s) {
   for (Flight& f : s->fl) {
     if (f.batch) svd_batch_destroy(f.batch);
-    if (f.done) hipEventDestroy(f.done);
-    if (f.stream && f.stream != s->plain) hipStreamDestroy(f.stream);
+    if (f.done) (void)hipEventDestroy(f.done);
+    if (f.stream && f.stream != s->plain) (void)hipStreamDestroy(f.stream);
   }
-  if (s->plain) hipStreamDestroy(s->plain);
-  if (s->up_done) hipEventDestroy(s->up_done);
-  if (s->up) hipStreamDestroy(s->up);
+  if (s->plain) (void)hipStreamDestroy(s->plain);
+  if (s->up_done) (void)hipEventDestroy(s->up_done);
+  if (s->up) (void)hipStreamDestroy(s->up);
   delete s;
 }
 
@@ -582,8 +595,9 @@ extern "C" int svd_server_submit(svd_server* s, const svd_camera* cam, svd_hit* 
   if (s->sources != s->w->nchunks)
     return svd_fail(SVD_EINVAL, "serve: %u of %u chunks have no source", s->w->nchunks - s->sources, s->w->nchunks);
   if (!s->started) {
+    // chunk descriptions are on the device before any launch
+    if (hipStreamSynchronize(s->up) != hipSuccess) return svd_fail(SVD_EDEVICE, "serve: upload stream failed");
     s->started = true;
-    hipStreamSynchronize(s->up);  // chunk descriptions are on the device before any launch
   }
   r.t_submit = s->now();
   s->inbox.push_back(std::move(r));
