@@ -136,3 +136,22 @@ extern "C" int hk_trace(HkWorld* w, const svd_ray_frame* f, uint32_t flags, svd_
   for (auto& t : pool) t.join();
   return SVD_OK;
 }
+
+// The beam pass's cone test and distance for one tile and one cube, as the
+// kernels evaluate them: returns -1 for a degenerate cone, else 1 when the
+// cube [lo, lo + s] is dropped as outside the cone; *dist gets the cube's
+// distance bound in voxels.
+extern "C" int hk_beam_cube(const int64_t O[3], const int64_t A[3], const int64_t BX[3], const int64_t BY[3],
+                            uint32_t x0, uint32_t y0, uint32_t x1, uint32_t y1, const int32_t lo[3], int32_t s,
+                            uint32_t* dist) {
+  BeamParams bp;
+  memset(&bp, 0, sizeof(bp));
+  memcpy(bp.O, O, sizeof(bp.O));
+  memcpy(bp.A, A, sizeof(bp.A));
+  memcpy(bp.BX, BX, sizeof(bp.BX));
+  memcpy(bp.BY, BY, sizeof(bp.BY));
+  BeamCone q;
+  if (!beam_cone(bp, x0, y0, x1, y1, q)) return -1;
+  *dist = beam_dist(q, lo, s);
+  return beam_outside(q, lo, s) ? 1 : 0;
+}

@@ -47,6 +47,8 @@ def lib():
         L.hk_world_free.restype = None
         L.hk_upload.argtypes = [vp, u32, vp, ctypes.c_int]
         L.hk_trace.argtypes = [vp, vp, u32, vp, vp, u32]
+        L.hk_beam_cube.argtypes = [vp, vp, vp, vp, u32, u32, u32, u32, vp, ctypes.c_int32, vp]
+        L.hk_beam_cube.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -74,3 +76,14 @@ class HostWorld:
         view = np.zeros(self.n, np.uint32)
         assert lib().hk_trace(self.w, ctypes.byref(frame), flags, out.ctypes.data, view.ctypes.data, threads) == 0
         return out, view
+
+
+def beam_cube(O, A, BX, BY, tile, lo, s):
+    """(dropped, dist) of the beam pass for cube [lo, lo + s] and the tile with
+    pixel corners tile = (x0, y0, x1, y1); dropped is None for a degenerate
+    cone."""
+    i64 = ctypes.c_int64 * 3
+    d = ctypes.c_uint32(0)
+    r = lib().hk_beam_cube(i64(*O), i64(*A), i64(*BX), i64(*BY), *tile, (ctypes.c_int32 * 3)(*lo), s,
+                           ctypes.byref(d))
+    return (None if r < 0 else bool(r)), d.value
