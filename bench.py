@@ -10,7 +10,11 @@ Prints one JSON line (rank 0).  Besides the throughput it reports:
   roofline      for the trace kernel: algorithmic bytes per launch (mean
                 bytes per ray from the oracle's visit counts x rays) over the
                 kernel's mean duration (HIP events on its stream), against
-                the 8 TB/s HBM peak;
+                the 8 TB/s HBM peak; beside it the no-reuse bound (every read
+                a 64-B sector), the records' bytes (the compulsory floor) and
+                the HBM traffic the counters measured;
+  valu_issue    the trace kernel's VALU instructions (counters) per second
+                against the issue peak, and its lane utilisation;
   cpu_baseline  the CPU oracle timed on a bounded sample of the same views.
 """
 from __future__ import annotations
@@ -66,21 +70,25 @@ def counter_profile(workload):
     return vals
 
 
-def bytes_per_ray(counts, hits, lods, chunk_log2, n_rle):
+def bytes_per_ray(counts, hits, lods, chunk_log2, n_rle, sector=0):
     """Algorithmic bytes of the trace kernel for each ray (the canonical visit
     set that the oracle's counting mode replays):
     4 B view entry per chunk visited; 20 B per chunk DAG entered (node and
     leaf array addresses, root word); 4 B child word per internal node
     entered; 12 B (child word + bitmap) per leaf entered; at a hit 28 B
     (prefix and run array addresses, run count), 4 B per internal level
-    (DFS prefix), 4 B per run search step and 1 B material; the 16 B record."""
-    b = (4.0 * counts["chunk_visits"] + 20.0 * counts["chunk_entries"] +
-         4.0 * counts["node_cubes"] + 12.0 * counts["leaf_cubes"] + 16.0)
+    (DFS prefix), 4 B per run search step and 1 B material; the 16 B record.
+    With `sector` > 0, every one of those reads costs a whole sector of that
+    many bytes instead (the no-reuse upper bound; the record stays 16 B)."""
+    def rd(nbytes, accesses):
+        return sector * accesses if sector else nbytes
+    b = (rd(4.0, 1) * counts["chunk_visits"] + rd(20.0, 1) * counts["chunk_entries"] +
+         rd(4.0, 1) * counts["node_cubes"] + rd(12.0, 2) * counts["leaf_cubes"] + 16.0)
     h = hits["hit"] == 1
     k = hits["lod"][h]
     nr = n_rle[hits["chunk"][h], k]
     steps = np.ceil(np.log2(np.maximum(nr, 1)))
-    b[h] += 28.0 + 4.0 * (chunk_log2 - k - 2) + 4.0 * steps + 1.0
+    b[h] += rd(28.0, 1) + rd(4.0, 1) * (chunk_log2 - k - 2) + rd(4.0, 1) * steps + rd(1.0, 1)
     return b
 
 
@@ -145,6 +153,10 @@ def main():
     nch = gx * gy * gz
     cams = sw.views(args.views, 1)
     W, H = cams[0].width, cams[0].height
+    # The oracle (test infrastructure) runs only in this CPU-baseline leg:
+    # its own DAGs of the sampled views, its timing on the host cores, its
+    # visit counts (the algorithmic bytes of the roofline) and a spot check
+    # of view 0.  Nothing it computes reaches the GPU path.
     use_oracle = not args.no_cpu_baseline
 
     # ---- oracle side: which (chunk, LOD) DAGs the sampled views need
@@ -266,12 +278,14 @@ def main():
     if use_oracle:
         # ---- algorithmic bytes per ray: oracle visit counts on a sparse sample of every view
         stride = 97
-        per_ray = []
+        per_ray, per_ray_sec = [], []
         for v, f in enumerate(frames):
             idx = np.arange(v % stride, W * H, stride, dtype=np.uint32)
             h, cnt = ow.trace_frame(view_lods[v], f, idx, mode=1, threads=args.threads, counts=True)
             per_ray.append(bytes_per_ray(cnt, h, view_lods[v], CL, n_rle))
+            per_ray_sec.append(bytes_per_ray(cnt, h, view_lods[v], CL, n_rle, sector=64))
         mean_b = float(np.concatenate(per_ray).mean())
+        mean_b_sec = float(np.concatenate(per_ray_sec).mean())
         # per-view launches cycle over the views; weight each view's bytes by its launches
         nviews = len(frames)
         view_b = np.array([p.mean() for p in per_ray])
@@ -287,6 +301,11 @@ def main():
             "kernel": "beam_kernel + trace_kernel" if args.beam else "trace_kernel",
             "bytes_per_ray": round(mean_b, 2),
             "bytes_per_launch": round(bytes_per_launch), "launch_ms": round(float(pass_ms.mean()), 4),
+            # no-reuse upper bound: every read a whole 64-B sector
+            "sector64_bytes_per_ray": round(mean_b_sec, 2),
+            # compulsory lower bound: the records alone (unique DAG bytes come on top)
+            "record_bytes_per_launch": W * H * 16,
+            "blocks_per_cu": int(svdag.svd_world_get_occupancy(world)[0]),
         }
         if "l1_hit_rate" in prof:
             result["caches"] = {"l1_hit_rate": float(prof["l1_hit_rate"]), "l2_hit_rate": float(prof["l2_hit_rate"]),
@@ -298,6 +317,8 @@ def main():
             peak = 1024 * 2.4e9 / 4
             result["valu_issue"] = {"achieved": round(rate / 1e9, 2), "peak": round(peak / 1e9, 2),
                                     "unit": "G wave-instructions/s", "frac": round(rate / peak, 4)}
+            if "valu_lane_utilisation" in prof:
+                result["valu_issue"]["lane_utilisation"] = float(prof["valu_lane_utilisation"])
         # ---- CPU baseline: the oracle (as is) on a bounded sample: whole views
         #      in benchmark order while the time budget lasts, else evenly
         #      spaced pixels of view 0
