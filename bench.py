@@ -247,6 +247,19 @@ def main():
     rays = W * H * args.steps
     value = rays / t_total / 1e9
 
+    # beside the metric: views whose records are also copied to pinned host
+    # memory (stage + trace + D2H on the same stream), outside the timed region
+    host = torch.empty((W * H, 4), dtype=torch.int32, pin_memory=True)
+    nd2h = min(args.steps, 10)
+    evd = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(nd2h)]
+    for i in range(nd2h):
+        evd[i][0].record(stream)
+        step(i)
+        host.copy_(out, non_blocking=True)
+        evd[i][1].record(stream)
+    torch.cuda.synchronize()
+    d2h_ms = np.array([e[0].elapsed_time(e[1]) for e in evd])
+
     raw = out.cpu().numpy()
     hits = svdag.decode_hits(raw)
     assert not np.any(hits["chunk"] == svdag.FAULT_CHUNK), "iteration guard fired"
@@ -272,6 +285,9 @@ def main():
         "beam_kernel_ms_mean": round(float(beam_ms.mean()), 4),
         "stage_kernel_ms_mean": round(float(stage_ms.mean()), 4),
         "beam_pass": bool(args.beam),
+        "with_d2h": {"p50_view_ms": round(float(np.percentile(d2h_ms, 50)), 4),
+                     "grays": round(W * H / float(np.percentile(d2h_ms, 50)) / 1e6, 4),
+                     "note": "stage + trace + records to pinned host memory (PCIe), not the metric"},
         "hit_fraction": round(float(hits["hit"].mean()), 4),
     }
 
