@@ -67,11 +67,11 @@ def _build(svdag, torch, kind, seed, lod_count, thr, nviews, extra_cams=()):
     return sw, w, ow, cams, frames, vlods, blobs
 
 
-def _trace_like_bench(svdag, torch, w, cam):
+def _trace_like_bench(svdag, torch, w, cam, flags=0):
     f = svdag.svd_camera_frame(cam)
     out = torch.empty((f.width * f.height, 4), dtype=torch.int32, device="cuda")
     s = torch.cuda.current_stream()
-    svdag.svd_view_stage(w, f, 0, s)
+    svdag.svd_view_stage(w, f, flags, s)
     svdag.svd_view_trace(w, f, out, s)
     torch.cuda.synchronize()
     return out.cpu().numpy(), svdag.svd_view_table(w)
@@ -155,6 +155,19 @@ def test_map512_full_frames(env, map512):
         compare(svdag, raw, ref, label=f"map512 view {v}")
         lods_seen |= set(ref["lod"][ref["hit"] == 1].tolist())
     assert len(lods_seen) >= 2
+
+
+def test_map512_beam_pass_changes_no_record(env, map512):
+    """The exact beam pass on full 1440p map views: every record equals the
+    plain trace's (which the test above checks against the oracle)."""
+    svdag, torch = env
+    sw, w, ow, cams, frames, vlods, _ = map512
+    for v in range(3):
+        plain, _ = _trace_like_bench(svdag, torch, w, cams[v])
+        beam, _ = _trace_like_bench(svdag, torch, w, cams[v], flags=svdag.SVD_BEAM)
+        diff = int(np.count_nonzero((plain != beam).any(axis=1)))
+        note(f"map512 view {v}: beam pass, {diff} records differ")
+        assert diff == 0
 
 
 def test_map512_batch_of_64_sampled(env, map512):
