@@ -98,7 +98,12 @@ typedef struct {
  *          side the ray entered through (lowest axis on ties)
  *   t      Euclidean distance in voxels from the camera to where the ray
  *          enters the hit cell (float32); +inf on a miss
- *   chunk  linear chunk index cx + gx*(cy + gy*cz); 0xFFFFFFFF on a miss
+ *   chunk  linear chunk index cx + gx*(cy + gy*cz); 0xFFFFFFFF on a miss;
+ *          SVD_CHUNK_NOT_LOADED (below) when the ray reached a chunk whose
+ *          picked LOD is described but not resident; 0xFFFFFFFE if the chunk
+ *          walk's iteration guard fired (a ray crosses at most 3 x 4096
+ *          chunks, so it never fires; the walk inside a chunk ends by
+ *          construction)
  * A miss has xy = zf = 0. */
 typedef struct {
   uint32_t xy;

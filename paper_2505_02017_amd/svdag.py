@@ -24,7 +24,7 @@ SVD_ERANGE = -5
 SVD_ENOTFOUND = -6
 SVD_NO_CULL = 1
 SVD_BEAM = 2
-FAULT_CHUNK = 0xFFFFFFFE  # written by the trace if its iteration guard fires
+FAULT_CHUNK = 0xFFFFFFFE  # written by the trace if its chunk-walk iteration guard fires (never expected)
 CHUNK_NOT_LOADED = 0xFFFFFFFD  # a ray reached a chunk whose picked LOD is only described
 
 _NAMES = {SVD_EINVAL: "EINVAL", SVD_ENOMEM: "ENOMEM", SVD_EDEVICE: "EDEVICE",
