@@ -177,13 +177,16 @@ int svd_world_pool_used(const svd_world* w, size_t* used);
 
 /* Upload all LODs of `b` as chunk c (replacing what was there).  Enqueues an
  * H2D copy from the blob's memory on `stream`: the blob must stay alive and
- * unchanged until the stream has passed this point.  SVD_ENOMEM if the pool
- * has no room (nothing is changed then); SVD_EINVAL if the blob's chunk size
- * or LOD count differ from the world's. */
+ * unchanged until the stream has passed this point.  Replacing a resident
+ * chunk releases its old space at once, so the caller orders this call after
+ * every trace that still reads the chunk (same stream, or an event wait).
+ * SVD_ENOMEM if the pool has no room (nothing is changed then); SVD_EINVAL if
+ * the blob's chunk size or LOD count differ from the world's. */
 int svd_chunk_upload(svd_world* w, const uint32_t c[3], const svd_blob* b, void* stream);
-/* Release chunk c's pool space; the chunk counts as never uploaded again.
- * Work already enqueued on the world's stream still sees the old data
- * (stream order). */
+/* Release chunk c's pool space; the chunk counts as never uploaded again
+ * (traces refuse to run until it is).  No device work is enqueued: traces
+ * already enqueued still read the old data, so the caller orders later
+ * uploads that may reuse the space after them (as for svd_chunk_evict_lods). */
 int svd_chunk_evict(svd_world* w, const uint32_t c[3]);
 
 /* Per-LOD residency, for streaming (Section 3.4: LODs are loaded and
