@@ -243,7 +243,9 @@ def main():
     beam_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
     trace_ms = np.array([e[2].elapsed_time(e[3]) for e in evs])
     view_ms = stage_ms + beam_ms + trace_ms
-    pass_ms = beam_ms + trace_ms  # the trace pass: beam kernel + trace kernel
+    # the trace pass: beam kernel + trace kernel (without the beam, the event
+    # pair around the beam call brackets no kernel)
+    pass_ms = beam_ms + trace_ms if args.beam else trace_ms
     rays = W * H * args.steps
     value = rays / t_total / 1e9
 
