@@ -189,6 +189,46 @@ __host__ __device__ __forceinline__ bool exit_cell(Ray& r, const uint32_t E[3], 
   return true;
 }
 
+// One level down: the child of cell c (level lev, exit numerators E) that
+// holds the current instant, by three mid-plane tests.  Updates c, E and lev
+// to the child and returns its octant in the unmirrored node.
+__host__ __device__ __forceinline__ uint32_t descend(const Ray& r, int32_t c[3], uint32_t E[3], int& lev) {
+  const uint32_t half = 1u << (lev - 1 + 16);
+  uint32_t bits = 0;
+  _Pragma("unroll") for (int a = 0; a < 3; a++) {
+    const uint32_t nm = E[a] - half;  // mid-plane numerator
+    const uint32_t b = (uint32_t)(E[a] < half) | (uint32_t)r.past_n(a, nm);
+    c[a] = 2 * c[a] + (int32_t)b;
+    E[a] = b ? E[a] : nm;
+    bits |= b << a;
+  }
+  lev--;
+  return bits ^ r.mm;
+}
+
+// Enter the non-empty child `oct` (a cube at level lev) of the current node:
+// a node or leaf word from the DAG (node words of levels >= k + 3 go on the
+// path stack; a leaf's word carries its sub-block summary, and its bitmap is
+// read), or a sub-block of the current leaf.  `mask` becomes the child's
+// children mask.
+__host__ __device__ __forceinline__ void enter_child(int lev, int k, uint32_t oct, uint32_t& mask, uint32_t& ptr,
+                                                     uint32_t& lmask, uint64_t& bitmap, gptr32 nodes, gptr64 leaves,
+                                                     uint32_t* stk, uint32_t ss) {
+  if (lev >= k + 2) {
+    const uint32_t w = nodes[ptr + __builtin_popcount(mask & ((1u << oct) - 1u))];
+    mask = w >> kPtrBits;
+    ptr = w & kPtrMask;
+    if (lev >= k + 3) {
+      stk[(lev - 3) * ss] = w;
+    } else {
+      lmask = mask;
+      bitmap = leaves[ptr];
+    }
+  } else {
+    mask = (uint32_t)(bitmap >> (8 * oct)) & 0xFFu;
+  }
+}
+
 // The whole per-pixel path: ray setup, world entry, chunk walk, DAG
 // traversal, hit resolve.  `stk` is this ray's node-word stack (levels 3..10,
 // element stride `ss`).
@@ -278,34 +318,19 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
       ptr = 0;
       // DAG walk inside the chunk, until a hit or the ray leaves the chunk
       for (;;) {
-        // descend: the child of cell c (level lev) holding the current instant
-        const uint32_t half = 1u << (lev - 1 + 16);
-        uint32_t bits = 0;
-        _Pragma("unroll") for (int a = 0; a < 3; a++) {
-          const uint32_t nm = E[a] - half;  // mid-plane numerator
-          const uint32_t b = (uint32_t)(E[a] < half) | (uint32_t)r.past_n(a, nm);
-          c[a] = 2 * c[a] + (int32_t)b;
-          E[a] = b ? E[a] : nm;
-          bits |= b << a;
-        }
-        lev--;
-        const uint32_t oct = bits ^ r.mm;  // octant in the unmirrored node
+        uint32_t oct = descend(r, c, E, lev);
         if ((mask >> oct) & 1u) {
           if (lev == k) { status = kHit; break; }
-          if (lev >= k + 2) {
-            const uint32_t w = nodes[ptr + __builtin_popcount(mask & ((1u << oct) - 1u))];
-            mask = w >> kPtrBits;
-            ptr = w & kPtrMask;
-            if (lev >= k + 3) {
-              stk[(lev - 3) * ss] = w;
-            } else {  // a leaf: its word carries the sub-block summary
-              lmask = mask;
-              bitmap = leaves[ptr];
-            }
-          } else {
-            mask = (uint32_t)(bitmap >> (8 * oct)) & 0xFFu;
+          enter_child(lev, k, oct, mask, ptr, lmask, bitmap, nodes, leaves, stk, ss);
+          // A second descent in the same iteration: lanes that go on down
+          // use the issue slots in which the lanes leaving an empty cell run
+          // the longer exit path (divergent lanes of a wave run both).
+          oct = descend(r, c, E, lev);
+          if ((mask >> oct) & 1u) {
+            if (lev == k) { status = kHit; break; }
+            enter_child(lev, k, oct, mask, ptr, lmask, bitmap, nodes, leaves, stk, ss);
+            continue;
           }
-          continue;
         }
         // the child is empty: leave it through its earliest exit plane (no
         // iteration guard here: each exit moves the cell forward on some axis
