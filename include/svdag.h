@@ -326,7 +326,9 @@ int svd_batch_tune(svd_batch* b, const svd_camera* cams, uint32_t n, svd_hit* ou
  *     views and max_rays rays) into captured batch launches, up to
  *     `inflight` of them on the device at once, each on its own stream;
  *     requests arriving meanwhile join the next launch as soon as a launch
- *     slot frees (continuous batching);
+ *     slot frees (continuous batching); a launch that holds one request runs
+ *     the per-view kernels on its batch's tables instead of the graph (no
+ *     upload first);
  *   - SVD_SERVE_PLAIN traces each request with its own stage + trace launch
  *     pair, all on one stream, up to `inflight` queued (the per-request
  *     comparison);

@@ -733,8 +733,16 @@ int launch_beam(const BeamParams& p, void* stream) {
 // view from one work queue, so small views fill the machine as well as large
 // ones.  All per-batch values come from device memory (BatchHeader and
 // BatchView), so the three launches are captured once as a graph.
+// Zero the queue counters and the done counter that follows them.
 __global__ void batch_reset_kernel(uint32_t* queue) {
-  if (threadIdx.x < kQueues) queue[threadIdx.x * kQueueStride] = 0;
+  if (threadIdx.x <= kQueues) queue[threadIdx.x * kQueueStride] = 0;
+}
+
+int launch_queue_clear(uint32_t* queue, void* stream) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, queue);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return svd_fail(SVD_EDEVICE, "queue clear launch: %s", hipGetErrorString(e));
+  return SVD_OK;
 }
 
 __global__ void batch_stage_kernel(BatchParams p) {

@@ -410,6 +410,59 @@ StageParams world_stage_params(const svd_world* w, const svd_ray_frame* f, bool 
   return sp;
 }
 
+// Per-view beam and trace parameters: 16x4-pixel tiles over the frame, the
+// given view table (per-chunk LOD and flags) and, for the trace, the given
+// queue block.
+static BeamParams view_beam_params(const svd_world* w, const svd_ray_frame* f, const uint32_t* view, svd_hit* out) {
+  BeamParams bp;
+  memset(&bp, 0, sizeof(bp));
+  memcpy(bp.O, f->O, sizeof(bp.O));
+  memcpy(bp.A, f->A, sizeof(bp.A));
+  memcpy(bp.BX, f->BX, sizeof(bp.BX));
+  memcpy(bp.BY, f->BY, sizeof(bp.BY));
+  bp.W = f->width;
+  bp.H = f->height;
+  bp.tiles_x = (f->width + kViewTileW - 1) / kViewTileW;
+  const uint64_t th = 64 / kViewTileW;
+  bp.total_tiles = (uint32_t)((uint64_t)bp.tiles_x * ((f->height + th - 1) / th));
+  bp.tile_w = kViewTileW;
+  memcpy(bp.grid, w->desc.grid, sizeof(bp.grid));
+  bp.chunk_log2 = w->desc.chunk_log2;
+  bp.view = view;
+  bp.desc = w->d_desc;
+  bp.out = out;
+  return bp;
+}
+
+static TraceParams view_trace_params(const svd_world* w, const svd_ray_frame* f, uint32_t* queue,
+                                     const uint32_t* view, svd_hit* out, bool beam) {
+  TraceParams tp;
+  memset(&tp, 0, sizeof(tp));
+  memcpy(tp.O, f->O, sizeof(tp.O));
+  memcpy(tp.A, f->A, sizeof(tp.A));
+  memcpy(tp.BX, f->BX, sizeof(tp.BX));
+  memcpy(tp.BY, f->BY, sizeof(tp.BY));
+  tp.W = f->width;
+  tp.H = f->height;
+  memcpy(tp.grid, w->desc.grid, sizeof(tp.grid));
+  tp.chunk_log2 = w->desc.chunk_log2;
+  tp.tiles_x = (f->width + kViewTileW - 1) / kViewTileW;
+  const uint64_t th = 64 / kViewTileW;
+  tp.total_tiles = (uint32_t)((uint64_t)tp.tiles_x * ((f->height + th - 1) / th));
+  tp.queue = queue;
+  tp.view = view;
+  tp.desc = w->d_desc;
+  tp.out = out;
+  tp.beam = beam;
+  return tp;
+}
+
+// A persistent grid at the world's occupancy, but no more waves (4 per
+// block) than there are tiles.
+static uint32_t view_trace_blocks(const svd_world* w, const TraceParams& tp) {
+  return (uint32_t)std::min<uint64_t>((uint64_t)w->per_cu * w->cus, (tp.total_tiles + 3) / 4);
+}
+
 extern "C" int svd_view_stage(svd_world* w, const svd_ray_frame* f, uint32_t flags, void* stream) {
   if (!w || !f) return svd_fail(SVD_EINVAL, "svd_view_stage: null argument");
   if (flags & ~(SVD_NO_CULL | SVD_BEAM)) return svd_fail(SVD_EINVAL, "stage: unknown flags");
@@ -433,24 +486,7 @@ extern "C" int svd_view_beam(svd_world* w, const svd_ray_frame* f, svd_hit* out_
     return svd_fail(SVD_EINVAL, "beam: the frame was not staged by the last svd_view_stage");
   if (w->absent) return svd_fail(SVD_ENOTFOUND, "beam: %u (chunk, LOD) slots were never uploaded", w->absent);
   if (!w->staged_beam) return SVD_OK;
-  BeamParams bp;
-  memset(&bp, 0, sizeof(bp));
-  memcpy(bp.O, f->O, sizeof(bp.O));
-  memcpy(bp.A, f->A, sizeof(bp.A));
-  memcpy(bp.BX, f->BX, sizeof(bp.BX));
-  memcpy(bp.BY, f->BY, sizeof(bp.BY));
-  bp.W = f->width;
-  bp.H = f->height;
-  bp.tiles_x = (f->width + kViewTileW - 1) / kViewTileW;
-  const uint64_t th = 64 / kViewTileW;
-  bp.total_tiles = (uint32_t)((uint64_t)bp.tiles_x * ((f->height + th - 1) / th));
-  bp.tile_w = kViewTileW;
-  memcpy(bp.grid, w->desc.grid, sizeof(bp.grid));
-  bp.chunk_log2 = w->desc.chunk_log2;
-  bp.view = w->d_view;
-  bp.desc = w->d_desc;
-  bp.out = out_dev;
-  const int rc = launch_beam(bp, stream);
+  const int rc = launch_beam(view_beam_params(w, f, w->d_view, out_dev), stream);
   if (rc == SVD_OK) w->beamed = out_dev;
   return rc;
 }
@@ -460,33 +496,13 @@ extern "C" int svd_view_trace(svd_world* w, const svd_ray_frame* f, svd_hit* out
   if (!w->has_staged || !same_frame(w->staged, *f))
     return svd_fail(SVD_EINVAL, "trace: the frame was not staged by the last svd_view_stage");
   if (w->absent) return svd_fail(SVD_ENOTFOUND, "trace: %u (chunk, LOD) slots were never uploaded", w->absent);
-  const uint32_t W = f->width, H = f->height;
-  TraceParams tp;
-  memset(&tp, 0, sizeof(tp));
-  memcpy(tp.O, f->O, sizeof(tp.O));
-  memcpy(tp.A, f->A, sizeof(tp.A));
-  memcpy(tp.BX, f->BX, sizeof(tp.BX));
-  memcpy(tp.BY, f->BY, sizeof(tp.BY));
-  tp.W = W;
-  tp.H = H;
-  memcpy(tp.grid, w->desc.grid, sizeof(tp.grid));
-  tp.chunk_log2 = w->desc.chunk_log2;
-  tp.tiles_x = (W + kViewTileW - 1) / kViewTileW;
-  const uint64_t th = 64 / kViewTileW;
-  tp.total_tiles = (uint32_t)((uint64_t)tp.tiles_x * ((H + th - 1) / th));
-  tp.queue = w->d_queue;
-  tp.view = w->d_view;
-  tp.desc = w->d_desc;
-  tp.out = out_dev;
-  tp.beam = w->staged_beam;
+  const TraceParams tp = view_trace_params(w, f, w->d_queue, w->d_view, out_dev, w->staged_beam);
   if (tp.beam && w->beamed != out_dev) {  // per-tile start bounds, parked in each tile's first record
     const int rc = svd_view_beam(w, f, out_dev, stream);
     if (rc) return rc;
   }
   w->beamed = nullptr;
-  // a persistent grid, but no more waves (4 per block) than there are tiles
-  const uint32_t blocks = std::min<uint64_t>((uint64_t)w->per_cu * w->cus, (tp.total_tiles + 3) / 4);
-  return launch_trace(tp, blocks, stream);
+  return launch_trace(tp, view_trace_blocks(w, tp), stream);
 }
 
 extern "C" int svd_world_set_occupancy(svd_world* w, uint32_t blocks_per_cu) {
@@ -710,6 +726,33 @@ int batch_enqueue(svd_batch* b, const svd_ray_frame* frames, svd_hit* const* out
   HIP_OK(hipEventRecord(b->staged, s));
   b->stage_pending = true;
   HIP_OK(hipGraphLaunch(b->exec, s));
+  HIP_OK(hipEventRecord(b->finished, s));
+  b->launched = true;
+  return SVD_OK;
+}
+
+int batch_enqueue_single(svd_batch* b, const svd_ray_frame* f, svd_hit* out, uint32_t flags, hipStream_t s) {
+  if (flags & ~(SVD_NO_CULL | SVD_BEAM)) return svd_fail(SVD_EINVAL, "batch: unknown flags");
+  if (!out) return svd_fail(SVD_EINVAL, "batch: null output");
+  svd_world* w = b->w;
+  if (w->absent) return svd_fail(SVD_ENOTFOUND, "batch: %u (chunk, LOD) slots were never uploaded", w->absent);
+  int rc = check_frame(f);
+  if (rc) return rc;
+  // the graph's trace leaves its counters where they ended: start from zero
+  rc = launch_queue_clear(b->d_queue, s);
+  if (rc) return rc;
+  StageParams sp = world_stage_params(w, f, flags & SVD_NO_CULL, w->d_desc);
+  sp.view = b->d_tables;
+  rc = launch_chunk_stage(sp, s);
+  if (rc) return rc;
+  const bool beam = (flags & SVD_BEAM) != 0;
+  if (beam) {
+    rc = launch_beam(view_beam_params(w, f, b->d_tables, out), s);
+    if (rc) return rc;
+  }
+  const TraceParams tp = view_trace_params(w, f, b->d_queue, b->d_tables, out, beam);
+  rc = launch_trace(tp, view_trace_blocks(w, tp), s);
+  if (rc) return rc;
   HIP_OK(hipEventRecord(b->finished, s));
   b->launched = true;
   return SVD_OK;

@@ -387,7 +387,9 @@ static int enqueue(svd_server* s, Flight& f) {
   if (s->up_pending && hipStreamWaitEvent(f.stream, s->up_done, 0) != hipSuccess)
     return svd_fail(SVD_EDEVICE, "serve: stream wait");
   int rc = SVD_OK;
-  if (f.batch) {
+  if (f.batch && f.reqs.size() == 1) {  // nothing to pack: the batch's tables without the graph
+    rc = batch_enqueue_single(f.batch, &f.reqs[0].frame, f.reqs[0].out, f.reqs[0].flags, f.stream);
+  } else if (f.batch) {
     std::vector<svd_ray_frame> frames;
     std::vector<svd_hit*> outs;
     for (const Request& r : f.reqs) {

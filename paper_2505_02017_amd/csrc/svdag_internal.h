@@ -178,6 +178,9 @@ int launch_set_desc(DevDag* dst, const DevDag* src4, uint32_t n, void* stream);
 // batched views: queue reset, per-(view, chunk) stage, persistent trace
 int launch_batch(const BatchParams& p, uint32_t trace_blocks, void* stream);
 int batch_trace_occupancy(uint32_t* blocks_per_cu);
+// zero a queue block's counters and its done counter (a per-view trace on it
+// then starts from zero and clears it again when it ends)
+int launch_queue_clear(uint32_t* queue, void* stream);
 
 }  // namespace svd
 
@@ -304,3 +307,8 @@ struct svd_batch {
 // the caller's).
 int batch_enqueue(svd_batch* b, const svd_ray_frame* frames, svd_hit* const* outs, uint32_t n, uint32_t flags,
                   hipStream_t stream);
+// One view on a batch's own view table and queue block, without the graph:
+// queue clear, the per-view stage, beam (with SVD_BEAM) and trace kernels,
+// parameters as kernel arguments.  Same records as a one-view batch; for a
+// launch that holds a single view it skips the header upload.
+int batch_enqueue_single(svd_batch* b, const svd_ray_frame* frame, svd_hit* out, uint32_t flags, hipStream_t stream);

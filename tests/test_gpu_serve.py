@@ -186,6 +186,43 @@ def test_server_results_equal_alone(env, world, mode, views, inflight, tight, sf
         assert st["launches"] <= len(cams)
 
 
+def test_server_single_view_launches_then_burst(env, world):
+    """Batched mode where each launch holds one request (the batch's tables
+    without its graph), with and without the beam pass and culling, then a
+    burst that packs several views per launch over the same batch areas:
+    every request equals its view traced alone."""
+    svdag, torch = env
+    sw, blobs, ref_w = world
+    cams = _cams(sw, 31, 12)
+    flag_set = [0, svdag.SVD_NO_CULL, svdag.SVD_BEAM, svdag.SVD_NO_CULL | svdag.SVD_BEAM]
+    w = _server_world(svdag, torch, sw, 1 << 22, 6, 2)
+    s = svdag.svd_server_create(w, mode=0, max_views=6, inflight=2, max_rays=40000)
+    for ci, b in blobs.items():
+        svdag.svd_server_set_chunk(s, _coords(sw, ci), b)
+    outs = [torch.full((c.width * c.height, 4), -1, dtype=torch.int32, device="cuda") for c in cams * 2]
+    torch.cuda.synchronize()
+    flags = [flag_set[i % 4] for i in range(len(outs))]
+    for i, c in enumerate(cams):                     # one at a time: single-view launches
+        svdag.svd_server_submit(s, c, outs[i], tag=i, flags=flags[i])
+        got = []
+        while not got:
+            got = svdag.svd_server_poll(s, wait_us=100000)
+        assert got[0]["tag"] == i and got[0]["status"] == 0 and got[0]["batch_views"] == 1
+    for i, c in enumerate(cams):                     # a burst with one flag: packed launches
+        svdag.svd_server_submit(s, c, outs[len(cams) + i], tag=len(cams) + i, flags=svdag.SVD_NO_CULL)
+        flags[len(cams) + i] = svdag.SVD_NO_CULL
+    done = []
+    t0 = time.time()
+    while len(done) < len(cams) and time.time() - t0 < 60:
+        done += svdag.svd_server_poll(s, wait_us=100000)
+    svdag.svd_server_destroy(s)
+    torch.cuda.synchronize()
+    assert len(done) == len(cams) and all(d["status"] == 0 for d in done)
+    assert max(d["batch_views"] for d in done) > 1
+    for i, c in enumerate(cams * 2):
+        assert np.array_equal(outs[i].cpu().numpy(), _alone(svdag, torch, ref_w, c, flags[i])), f"request {i}"
+
+
 def test_server_culled_views_and_oversized_requests(env, world):
     svdag, torch = env
     sw, blobs, ref_w = world
