@@ -101,6 +101,11 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        # PyTorch ships its own HIP runtime under the same soname: load it
+        # first so that the library binds to it.  Loaded the other way round,
+        # the process would hold two HIP runtimes, and the library's would not
+        # see the device or the memory that torch allocates.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, u32, i32, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_size_t
         L.svd_last_error.restype = ctypes.c_char_p

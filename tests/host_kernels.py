@@ -39,6 +39,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB):
             raise ImportError(f"{LIB} is missing: build it with __graft_entry__.build()")
+        import torch  # noqa: F401  (its HIP runtime first: one runtime per process)
         L = ctypes.CDLL(LIB)
         vp, u32 = ctypes.c_void_p, ctypes.c_uint32
         L.hk_world_new.restype = vp
