@@ -11,8 +11,9 @@ Prints one JSON line (rank 0).  Besides the throughput it reports:
                 bytes per ray from the oracle's visit counts x rays) over the
                 kernel's mean duration (HIP events on its stream), against
                 the 8 TB/s HBM peak; beside it the no-reuse bound (every read
-                a 64-B sector), the records' bytes (the compulsory floor) and
-                the HBM traffic the counters measured;
+                a 64-B sector), the compulsory bytes (each touched byte once,
+                from the oracle's touch count) and the HBM traffic the
+                counters measured;
   valu_issue    the trace kernel's VALU instructions (counters) per second
                 against the issue peak, and its lane utilisation;
   cpu_baseline  the CPU oracle timed on a bounded sample of the same views.
@@ -309,6 +310,16 @@ def main():
         view_b = np.array([p.mean() for p in per_ray])
         launches = np.bincount(np.arange(args.steps) % nviews, minlength=nviews)
         bytes_per_launch = float((view_b * launches).sum() / launches.sum()) * W * H
+        # compulsory bytes: every part of the device layout a view's rays
+        # touch, counted once (child words, leaf bitmaps, prefix counts, run
+        # starts and materials, view-table entries, 64-B descriptors), plus
+        # the records
+        comp = []
+        for v, f in enumerate(frames):
+            t = ow.touch_frame(view_lods[v], f, threads=args.threads)
+            comp.append(4 * t["child_words"] + 8 * t["leaves"] + 4 * t["prefixes"] + 4 * t["run_starts"] +
+                        t["run_materials"] + 4 * t["chunks"] + 64 * t["dags"] + 16 * t["rays"])
+        compulsory = float((np.array(comp, np.float64) * launches).sum() / launches.sum())
         achieved = bytes_per_launch / (pass_ms.mean() * 1e-3) / 1e9
         prof = counter_profile(args.workload)
         traffic = float(prof["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in prof else None
@@ -321,7 +332,8 @@ def main():
             "bytes_per_launch": round(bytes_per_launch), "launch_ms": round(float(pass_ms.mean()), 4),
             # no-reuse upper bound: every read a whole 64-B sector
             "sector64_bytes_per_ray": round(mean_b_sec, 2),
-            # compulsory lower bound: the records alone (unique DAG bytes come on top)
+            # compulsory lower bound: each touched byte once (records included)
+            "compulsory_bytes_per_launch": round(compulsory),
             "record_bytes_per_launch": W * H * 16,
             "blocks_per_cu": int(svdag.svd_world_get_occupancy(world)[0]),
         }

@@ -59,6 +59,11 @@ def build(verbose: bool = False) -> str:
     return out
 
 
+class _Touched(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("rays", "hits", "child_words", "leaves", "prefixes",
+                                               "run_starts", "run_materials", "chunks", "dags")]
+
+
 def _lib():
     global _LIB
     if _LIB is None:
@@ -89,6 +94,8 @@ def _lib():
         L.or_lod_pick.argtypes = [vp, vp, vp, vp]
         L.or_trace.argtypes = [vp, vp, vp, vp, u32, vp, i32, i32]
         L.or_trace_frame.argtypes = [vp, vp, ctypes.POINTER(_Frame), vp, u32, vp, i32, i32, vp]
+        L.or_touch_frame.argtypes = [vp, vp, ctypes.POINTER(_Frame), i32, ctypes.POINTER(_Touched)]
+        L.or_touch_frame.restype = None
         _LIB = L
     return _LIB
 
@@ -279,6 +286,16 @@ class World:
         out = np.zeros(D.shape[0], HIT_DTYPE)
         _lib().or_trace(self._p, _ptr(lods), _ptr(O), _ptr(D), D.shape[0], _ptr(out), mode, threads)
         return out
+
+    def touch_frame(self, lods, frame: Frame, threads=1) -> dict:
+        """Counting instrumentation: the parts of the device layout that the
+        frame's rays touch, each counted once (child words, leaf bitmaps,
+        prefix counts, run starts and materials, view-table entries, DAG
+        descriptors), with the ray and hit counts."""
+        lods = np.ascontiguousarray(lods, np.uint8)
+        t = _Touched()
+        _lib().or_touch_frame(self._p, _ptr(lods), ctypes.byref(frame._f), threads, ctypes.byref(t))
+        return {n: int(getattr(t, n)) for n, _ in _Touched._fields_}
 
     def trace_frame(self, lods, frame: Frame, idx=None, mode=1, threads=1, counts=False):
         """Hits of the frame's pixels (all, or the indices `idx`).  With

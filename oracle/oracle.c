@@ -433,12 +433,38 @@ void or_dag_free(or_dag* d) {
   free(d);
 }
 
+/* Touch marks of one DAG (counting instrumentation, see or_touch_frame):
+ * child pointers read on the way down, leaf bitmaps read, child pointers of
+ * a solid cell's path (whose prefix counts a hit reads), run starts probed
+ * and run materials read.  NULL arrays mark nothing. */
+typedef struct {
+  uint8_t* words;   /* [n_words]: child pointer read */
+  uint8_t* pre;     /* [n_words]: prefix of this child read (hit paths) */
+  uint8_t* leaves;  /* [n_leaves] */
+  uint8_t* rle;     /* [n_rle]: run start probed */
+  uint8_t* mat;     /* [n_rle]: run material read */
+} or_marks;
+
+static void mark(uint8_t* m, uint32_t i) {
+  if (m) __atomic_store_n(&m[i], (uint8_t)1, __ATOMIC_RELAXED);
+}
+
+static int dag_lookup(const or_dag* d, uint32_t x, uint32_t y, uint32_t z, uint32_t* dfs,
+                      uint32_t* empty_level, const or_marks* mk);
+
 /* Point query.  The DFS index is the sum, along the root-to-leaf path, of the
  * subtree counts of the preceding siblings, plus the set bits below the
  * cell's bit in its leaf bitmap (Section 3.3). */
 int or_dag_lookup(const or_dag* d, uint32_t x, uint32_t y, uint32_t z, uint32_t* dfs,
                   uint32_t* empty_level) {
+  return dag_lookup(d, x, y, z, dfs, empty_level, NULL);
+}
+
+static int dag_lookup(const or_dag* d, uint32_t x, uint32_t y, uint32_t z, uint32_t* dfs,
+                      uint32_t* empty_level, const or_marks* mk) {
   if (d->n_words == 0) { *empty_level = d->root_level; return 0; }
+  uint32_t path[16];
+  uint32_t np = 0;
   uint32_t off = 0, acc = 0;
   for (uint32_t l = d->root_level; l >= 3; l--) {
     const uint32_t mask = d->words[off];
@@ -453,8 +479,13 @@ int or_dag_lookup(const or_dag* d, uint32_t x, uint32_t y, uint32_t z, uint32_t*
       slot++;
     }
     const uint32_t ptr = d->words[off + 2 + slot];
+    if (mk) {
+      mark(mk->words, off + 2 + slot);
+      path[np++] = off + 2 + slot;
+    }
     if (l == 3) {
       const uint64_t bits = d->leaves[ptr];
+      if (mk) mark(mk->leaves, ptr);
       const int o1 = (int)(((x >> 1) & 1) | (((y >> 1) & 1) << 1) | (((z >> 1) & 1) << 2));
       const int o0 = (int)((x & 1) | ((y & 1) << 1) | ((z & 1) << 2));
       if (!((bits >> (8 * o1)) & 0xFF)) { *empty_level = 1; return 0; }
@@ -462,6 +493,10 @@ int or_dag_lookup(const or_dag* d, uint32_t x, uint32_t y, uint32_t z, uint32_t*
       if (!((bits >> b) & 1)) { *empty_level = 0; return 0; }
       acc += (uint32_t)__builtin_popcountll(bits & ((1ull << b) - 1));
       *dfs = acc;
+      /* a hit reads the prefix count of every child on its path, from the
+       * root's child down to the leaf (one per internal level) */
+      if (mk)
+        for (uint32_t i = 0; i < np; i++) mark(mk->pre, path[i]);
       return 1;
     }
     off = ptr;
@@ -469,13 +504,19 @@ int or_dag_lookup(const or_dag* d, uint32_t x, uint32_t y, uint32_t z, uint32_t*
   return 0; /* not reached: root_level >= 3 */
 }
 
+static uint8_t dag_material(const or_dag* d, uint32_t i, const or_marks* mk);
+
 /* Material of DFS index i: the run block with the largest start <= i. */
-uint8_t or_dag_material(const or_dag* d, uint32_t i) {
+uint8_t or_dag_material(const or_dag* d, uint32_t i) { return dag_material(d, i, NULL); }
+
+static uint8_t dag_material(const or_dag* d, uint32_t i, const or_marks* mk) {
   uint32_t lo = 0, hi = d->n_rle; /* answer in [lo, hi) */
   while (hi - lo > 1) {
     uint32_t mid = lo + (hi - lo) / 2;
+    if (mk) mark(mk->rle, mid);
     if (d->rle_start[mid] <= i) lo = mid; else hi = mid;
   }
+  if (mk) mark(mk->mat, lo);
   return d->rle_mat[lo];
 }
 
@@ -641,6 +682,11 @@ typedef struct {
   const or_world* w;
   const uint8_t* lods;
   int mode;
+  /* touch instrumentation (NULL when off): marks per DAG [chunk * lod_count
+   * + lod], chunks visited and DAGs entered */
+  const or_marks* marks;
+  uint8_t* chunk_marks;
+  uint8_t* dag_marks;
 } or_tctx;
 
 /* Occupancy of world LOD-k cell c in chunk ci.  Returns 1 if solid (and the
@@ -662,7 +708,8 @@ static int occupied(const or_tctx* T, uint32_t ci, uint32_t k, const int64_t c[3
   const or_dag* d = w->dags[i];
   if (!d) { *skip = (T->mode & 1) ? w->chunk_log2 - k : 0; *elev = (int32_t)(w->chunk_log2 - k); return 0; }
   uint32_t dfs = 0, lev = 0;
-  if (or_dag_lookup(d, x, y, z, &dfs, &lev)) { *mat = or_dag_material(d, dfs); return 1; }
+  const or_marks* mk = T->marks ? &T->marks[i] : NULL;
+  if (dag_lookup(d, x, y, z, &dfs, &lev, mk)) { *mat = dag_material(d, dfs, mk); return 1; }
   *skip = (T->mode & 1) ? lev : 0;
   *elev = (int32_t)lev;
   return 0;
@@ -717,6 +764,8 @@ static void trace_one(const or_tctx* T, const int64_t O[3], const int64_t D[3], 
     int64_t prev[3] = {0, 0, 0};
     int have_prev = 0;
     if (cnt) cnt->chunk_visits++;
+    mark(T->chunk_marks, ci);
+    if (dk && dk->n_words) mark(T->dag_marks, (uint32_t)((size_t)ci * w->lod_count + k));
     const int64_t base[3] = {cc[0] << (CL - k), cc[1] << (CL - k), cc[2] << (CL - k)};
     int64_t c[3];
     for (int a = 0; a < 3; a++) c[a] = cell_at(O[a], D[a], cur, k);
@@ -816,7 +865,7 @@ static void run_jobs(or_job* base, uint32_t n, int nthreads) {
 
 void or_trace(const or_world* w, const uint8_t* lods, const int64_t O[3], const int32_t* D,
               uint32_t n, or_hit* out, int mode, int nthreads) {
-  or_tctx T = {w, lods, mode};
+  or_tctx T = {w, lods, mode, NULL, NULL, NULL};
   or_job J = {&T, NULL, O, D, NULL, NULL, 0, n, out};
   run_jobs(&J, n, nthreads);
 }
@@ -824,7 +873,51 @@ void or_trace(const or_world* w, const uint8_t* lods, const int64_t O[3], const 
 void or_trace_frame(const or_world* w, const uint8_t* lods, const or_frame* f,
                     const uint32_t* idx, uint32_t n, or_hit* out, int mode, int nthreads,
                     or_counts* counts) {
-  or_tctx T = {w, lods, mode};
+  or_tctx T = {w, lods, mode, NULL, NULL, NULL};
   or_job J = {&T, counts, NULL, NULL, f, idx, 0, n, out};
   run_jobs(&J, n, nthreads);
+}
+
+/* Counting instrumentation: the bytes of the device layout that the rays
+ * of a frame touch, each counted once (see oracle.h). */
+void or_touch_frame(const or_world* w, const uint8_t* lods, const or_frame* f, int nthreads,
+                    or_touched* out) {
+  const size_t nd = (size_t)w->nchunks * w->lod_count;
+  or_marks* mk = (or_marks*)calloc(nd, sizeof(or_marks));
+  for (size_t i = 0; i < nd; i++) {
+    const or_dag* d = w->dags[i];
+    if (!d) continue;
+    mk[i].words = (uint8_t*)calloc(d->n_words ? d->n_words : 1, 1);
+    mk[i].pre = (uint8_t*)calloc(d->n_words ? d->n_words : 1, 1);
+    mk[i].leaves = (uint8_t*)calloc(d->n_leaves ? d->n_leaves : 1, 1);
+    mk[i].rle = (uint8_t*)calloc(d->n_rle ? d->n_rle : 1, 1);
+    mk[i].mat = (uint8_t*)calloc(d->n_rle ? d->n_rle : 1, 1);
+  }
+  uint8_t* cm = (uint8_t*)calloc(w->nchunks, 1);
+  uint8_t* dm = (uint8_t*)calloc(nd, 1);
+  const uint32_t n = f->W * f->H;
+  or_hit* hits = (or_hit*)malloc((size_t)n * sizeof(or_hit));
+  or_tctx T = {w, lods, 1, mk, cm, dm};
+  or_job J = {&T, NULL, NULL, NULL, f, NULL, 0, n, hits};
+  run_jobs(&J, n, nthreads);
+  memset(out, 0, sizeof(*out));
+  out->rays = n;
+  for (uint32_t h = 0; h < n; h++) out->hits += hits[h].hit != 0;
+  for (size_t i = 0; i < nd; i++) {
+    const or_dag* d = w->dags[i];
+    if (!d) continue;
+    for (uint32_t j = 0; j < d->n_words; j++) {
+      out->child_words += mk[i].words[j];
+      out->prefixes += mk[i].pre[j];
+    }
+    for (uint32_t j = 0; j < d->n_leaves; j++) out->leaves += mk[i].leaves[j];
+    for (uint32_t j = 0; j < d->n_rle; j++) {
+      out->run_starts += mk[i].rle[j];
+      out->run_materials += mk[i].mat[j];
+    }
+    out->dags += dm[i];
+    free(mk[i].words); free(mk[i].pre); free(mk[i].leaves); free(mk[i].rle); free(mk[i].mat);
+  }
+  for (uint32_t c = 0; c < w->nchunks; c++) out->chunks += cm[c];
+  free(mk); free(cm); free(dm); free(hits);
 }

@@ -115,6 +115,19 @@ void or_trace_frame(const or_world* w, const uint8_t* lods, const or_frame* f,
                     const uint32_t* idx, uint32_t n, or_hit* out, int mode, int nthreads,
                     or_counts* counts);
 
+/* Counting instrumentation for the compulsory-traffic figure: trace every
+ * pixel of a frame (mode 1) and count, each once, the parts of the device
+ * layout its rays touch: child words read on descents, leaf bitmaps,
+ * prefix counts and run starts read by hits, run materials, the view-table
+ * entries of the chunks visited and the descriptors of the chunk DAGs
+ * entered. */
+typedef struct {
+  uint64_t rays, hits;
+  uint64_t child_words, leaves, prefixes, run_starts, run_materials, chunks, dags;
+} or_touched;
+void or_touch_frame(const or_world* w, const uint8_t* lods, const or_frame* f, int nthreads,
+                    or_touched* out);
+
 #ifdef __cplusplus
 }
 #endif
