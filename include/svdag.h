@@ -301,7 +301,7 @@ int svd_batch_set_tiling(svd_batch* b, uint32_t tile_w, uint32_t claim);
 int svd_batch_set_occupancy(svd_batch* b, uint32_t blocks_per_cu);
 int svd_batch_get_tiling(const svd_batch* b, uint32_t* tile_w, uint32_t* claim, uint32_t* blocks_per_cu);
 
-/* Autotuner: times every tiling candidate (tile width 8/16/32 x claim
+/* Autotuner: times every tiling candidate (tile width 8/16/32/64 x claim
  * 1/2/4) at the current occupancy, then every occupancy from the maximum
  * down to 2 blocks per CU at the best tiling, on this batch of cameras
  * (median of `reps` launches after one warm-up, HIP events on `stream`;

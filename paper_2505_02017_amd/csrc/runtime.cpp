@@ -817,7 +817,7 @@ extern "C" int svd_batch_tune(svd_batch* b, const svd_camera* cams, uint32_t n, 
     if (e0) (void)hipEventDestroy(e0);
     return svd_fail(SVD_EDEVICE, "tune: event create failed");
   }
-  const uint32_t widths[] = {8, 16, 32};
+  const uint32_t widths[] = {8, 16, 32, 64};
   const uint32_t claims[] = {1, 2, 4};
   uint32_t bw = b->tile_w, bc = b->claim, bo = b->per_cu;
   float best = 3.4e38f;

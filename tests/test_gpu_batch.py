@@ -112,7 +112,7 @@ def test_tuner_and_errors(env, world):
     b = svdag.svd_batch_create(w, 10)
     out = torch.empty((svdag.batch_records(cams), 4), dtype=torch.int32, device="cuda")
     tw, claim, occ, ms = svdag.svd_batch_tune(b, cams, out, reps=2)
-    assert tw in (8, 16, 32) and claim in (1, 2, 4) and occ >= 1 and ms > 0
+    assert tw in (8, 16, 32, 64) and claim in (1, 2, 4) and occ >= 1 and ms > 0
     svdag.svd_batch_trace(b, cams, out)
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), _per_view(svdag, torch, w, cams))
