@@ -38,6 +38,9 @@ WORKLOADS = {
     "map512": ("map512", 4, (256, 1024, 4096),
                "map512: 16x16x1 chunks of 512^3 (8192x8192x512) terrain+caves+boxes, 4 LODs, "
                "frustum culling, 2560x1440 rays, 10 seeded views"),
+    "map1024": ("map1024", 4, (256, 1024, 4096),
+                "map1024: 32x32x1 chunks of 1024^3 (32768x32768x1024) terrain+caves+boxes, 4 LODs, "
+                "frustum culling, 2560x1440 rays, 10 seeded views"),
     "terrain1024": ("terrain1024", 1, (256, 1024, 4096),
                     "terrain1024: one 1024^3 terrain chunk with caves, 1920x1080 rays, 10 seeded views"),
     "noise64": ("noise64", 1, (256, 1024, 4096),
@@ -123,6 +126,9 @@ def main():
                     help="streaming factor of the prefetching runs (0 = skip them)")
     ap.add_argument("--serve-speed", type=float, default=600.0,
                     help="walker speed, voxels/s (fast enough that the walkers' chunk sets outgrow the pool)")
+    ap.add_argument("--gen", choices=("host", "gpu"), default="host",
+                    help="generate the scene's chunks on the host or with the GPU copy of the generator "
+                         "(same bytes; gpu makes map1024 practical)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -178,9 +184,10 @@ def main():
     t0 = time.time()
     blobs = {}
 
-    def work(ci):
+    def work(ci, g=None):
         c = (ci % gx, (ci // gx) % gy, ci // (gx * gy))
-        g = sw.chunk(c, threads=1 if nch > 1 else args.threads)
+        if g is None:
+            g = sw.chunk(c, threads=1 if nch > 1 else args.threads)
         b = svdag.svd_chunk_build(g, CL, lod_count)
         odags = []
         if ow is not None and need[ci]:
@@ -189,8 +196,39 @@ def main():
                 odags.append((k, oracle.Dag(pyr[k], (1 << CL) >> k)))
         return ci, b, odags
 
+    def gpu_generated(ex):
+        """Chunks generated on the GPU one at a time (one S^3 device buffer),
+        copied to a host buffer and built by the pool; host buffers are
+        recycled as builds finish."""
+        import queue
+        S = 1 << CL
+        dev = torch.empty(S ** 3, dtype=torch.uint8, device="cuda")
+        free = queue.Queue()
+        for _ in range(args.threads + 2):
+            free.put(np.empty(S ** 3, np.uint8))
+        work_dev = None
+
+        def build_and_recycle(ci, g):
+            try:
+                return work(ci, g)
+            finally:
+                free.put(g)
+
+        import collections
+        futs = collections.deque()
+        for ci in range(nch):
+            g = free.get()
+            work_dev = sw.chunk_device((ci % gx, (ci // gx) % gy, ci // (gx * gy)), dev, work_dev)
+            torch.from_numpy(g).copy_(dev)  # synchronous on this stream
+            futs.append(ex.submit(build_and_recycle, ci, g))
+            while futs and futs[0].done():
+                yield futs.popleft().result()
+        while futs:
+            yield futs.popleft().result()
+
     with ThreadPoolExecutor(args.threads) as ex:
-        for ci, b, odags in ex.map(work, range(nch)):
+        results = gpu_generated(ex) if args.gen == "gpu" else ex.map(work, range(nch))
+        for ci, b, odags in results:
             blobs[ci] = b
             for k, d in odags:
                 n_rle[ci, k] = d.d.n_rle
@@ -281,7 +319,8 @@ def main():
         "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": wdesc, "chunks": nch, "chunk_edge": 1 << CL, "lods": lod_count,
-                   "width": W, "height": H, "views": len(cams), "seed": args.seed},
+                   "width": W, "height": H, "views": len(cams), "seed": args.seed,
+                   "chunks_generated_on": args.gen},
         "p50_view_ms": round(float(np.percentile(view_ms, 50)), 4),
         "p99_view_ms": round(float(np.percentile(view_ms, 99)), 4),
         "trace_kernel_ms_mean": round(float(trace_ms.mean()), 4),

@@ -50,6 +50,7 @@ def build_lib(verbose: bool = False) -> str:
 def build_all(verbose: bool = False):
     from . import scenes
     scenes.build(verbose)
+    scenes.build_gpu(verbose)
     return build_lib(verbose)
 
 

@@ -4,7 +4,10 @@ This module holds no part of the SVDAG method.  It only produces inputs that
 both the CPU oracle and the GPU library consume:
 
 * dense uint8 chunks (0 = empty, 1..255 = material ID; index
-  ``x + S*(y + S*z)``), from the C generator ``libscenegen.so``;
+  ``x + S*(y + S*z)``), from the C generator ``libscenegen.so``, or for the
+  terrain kinds from its GPU copy ``libscenegen_gpu.so`` straight into device
+  memory (the same bytes, used where a map is too large to generate on the
+  host in a reasonable time);
 * camera poses (position, target, up, vertical FOV, resolution) in float32;
 * tiny random worlds for exhaustive tests (numpy, seeded).
 
@@ -52,6 +55,51 @@ def build(verbose: bool = False) -> str:
     return out
 
 
+def gpu_lib_path() -> str:
+    return os.path.join(_HERE, "libscenegen_gpu.so")
+
+
+def build_gpu(verbose: bool = False) -> str:
+    """Compile the GPU copy of the terrain generator (hipcc, gfx950)."""
+    import subprocess
+
+    src = os.path.join(_HERE, "scenegen_gpu.hip")
+    out = gpu_lib_path()
+    cmd = [os.environ.get("HIPCC", "/opt/rocm/bin/hipcc"), "-O3", "-fPIC", "-std=c++17",
+           "-ffp-contract=off", "-Wall", "--offload-arch=gfx950",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-shared", "-fvisibility=hidden", "-o", out + ".tmp", src]
+    if verbose:
+        print(" ".join(cmd))
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"build failed: {' '.join(cmd)}\n{r.stdout}{r.stderr}")
+    os.replace(out + ".tmp", out)
+    return out
+
+
+_GPU_LIB = None
+
+
+def _gpu_lib():
+    global _GPU_LIB
+    if _GPU_LIB is None:
+        import torch  # noqa: F401  (load torch's HIP runtime first: one runtime per process)
+        p = gpu_lib_path()
+        if not os.path.exists(p):
+            raise RuntimeError(f"{p} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(p)
+        i64p, f64p = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
+        L.sgg_work_bytes.restype = ctypes.c_size_t
+        L.sgg_work_bytes.argtypes = [i64p, f64p, ctypes.c_uint32]
+        L.sgg_gen_chunk.restype = ctypes.c_int
+        L.sgg_gen_chunk.argtypes = [i64p, f64p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                    ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        _GPU_LIB = L
+    return _GPU_LIB
+
+
 def _lib():
     global _LIB
     if _LIB is None:
@@ -70,6 +118,8 @@ def _lib():
         L.sg_gen_chunk.restype = ctypes.c_int
         L.sg_gen_chunk.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                    ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int]
+        L.sg_world_params.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_void_p)]
         L.sg_splitmix64.restype = ctypes.c_uint64
         L.sg_splitmix64.argtypes = [ctypes.c_uint64]
         _LIB = L
@@ -146,6 +196,62 @@ class SceneWorld:
         if rc != 0:
             raise ValueError(f"chunk {c} out of range")
         return out
+
+    def _terrain_params(self):
+        """(ip, dp, boxes): the generator's parameters and its boxes as an
+        int32 array of rows {x0, y0, z0, x1, y1, z1, material, 0} in paint
+        order."""
+        if getattr(self, "_tp", None) is None:
+            ip = (ctypes.c_int64 * 6)()
+            dp = (ctypes.c_double * 2)()
+            bp = ctypes.c_void_p()
+            _lib().sg_world_params(self._h, ip, dp, ctypes.byref(bp))
+            nb = int(ip[5])
+            rec = np.dtype({"names": ["b", "m"], "formats": [("<i4", 6), "u1"], "offsets": [0, 24],
+                            "itemsize": 28})
+            raw = np.frombuffer(ctypes.string_at(bp.value, 28 * nb), dtype=rec) if nb else np.zeros(0, rec)
+            boxes = np.zeros((nb, 8), np.int32)
+            boxes[:, :6] = raw["b"]
+            boxes[:, 6] = raw["m"]
+            self._tp = (ip, dp, boxes)
+        return self._tp
+
+    def chunk_device(self, c, out, work=None, stream=None):
+        """Generate chunk c on the GPU into `out`, a contiguous uint8 device
+        tensor of S^3 bytes: the same bytes as chunk(c).  Terrain kinds only
+        (not noise64).  `work` is an optional uint8 device tensor reused as
+        workspace; the call enqueues on `stream` (torch's current stream if
+        None) and returns the workspace."""
+        import torch
+        L = _gpu_lib()
+        ip, dp, boxes = self._terrain_params()
+        S, cl = self.S, self.chunk_log2
+        if int(ip[0]) != 1:
+            raise ValueError(f"{self.kind}: the GPU generator covers the terrain kinds only")
+        if not all(0 <= int(c[a]) < self.grid[a] for a in range(3)):
+            raise ValueError(f"chunk {c} out of range")
+        if not (out.is_cuda and out.dtype == torch.uint8 and out.is_contiguous() and out.numel() == S ** 3):
+            raise ValueError("out must be a contiguous uint8 device tensor of S^3 bytes")
+        lo = [int(c[a]) * S for a in range(3)]
+        keep = np.ones(len(boxes), bool)
+        for a in range(3):
+            keep &= (boxes[:, a] < lo[a] + S) & (boxes[:, a + 3] > lo[a])
+        sel = np.ascontiguousarray(boxes[keep])
+        s = stream if stream is not None else torch.cuda.current_stream(out.device)
+        need = int(L.sgg_work_bytes(ip, dp, cl))
+        if need == 0:
+            raise ValueError("bad generator parameters")
+        if work is None or work.numel() < need:
+            work = torch.empty(need, dtype=torch.uint8, device=out.device)
+        bd = torch.from_numpy(sel if len(sel) else np.zeros((1, 8), np.int32)).to(out.device)
+        with torch.cuda.stream(s):
+            rc = L.sgg_gen_chunk(ip, dp, ctypes.c_uint64(self.seed), cl, int(c[0]), int(c[1]), int(c[2]),
+                                 bd.data_ptr(), len(sel), out.data_ptr(), work.data_ptr(), work.numel(),
+                                 ctypes.c_void_p(s.cuda_stream))
+        bd.record_stream(s)
+        if rc != 0:
+            raise RuntimeError(f"sgg_gen_chunk failed ({rc})")
+        return work
 
     def height(self, x: int, y: int) -> int:
         return int(_lib().sg_height(self._h, int(x), int(y)))

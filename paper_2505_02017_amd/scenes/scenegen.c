@@ -194,6 +194,7 @@ typedef struct {
   int32_t x0, y0, z0, x1, y1, z1; /* inclusive-exclusive box in voxels */
   uint8_t mat;
 } sg_box;
+_Static_assert(sizeof(sg_box) == 28, "sg_world_params documents a 28-byte box record");
 
 typedef struct {
   int kind;
@@ -298,6 +299,18 @@ SG_EXPORT void sg_world_info(const sg_world* w, uint32_t* chunk_log2, uint32_t g
   *chunk_log2 = w->chunk_log2;
   grid[0] = w->grid[0]; grid[1] = w->grid[1]; grid[2] = w->grid[2];
   *nbox = w->nbox;
+}
+
+/* The parameters a second implementation of the terrain generator needs:
+ * ip = {terrain, centre, zmax, terrain_lam, cave_lam, nbox}, dp = {amp,
+ * cave_tau}; *boxes points at the world's nbox boxes in paint order (later
+ * boxes overwrite earlier ones), each 6 int32 bounds then the material byte,
+ * padded to 28 bytes.  The pointer stays valid while the world lives. */
+SG_EXPORT void sg_world_params(const sg_world* w, int64_t ip[6], double dp[2], const void** boxes) {
+  ip[0] = w->terrain; ip[1] = w->centre; ip[2] = w->zmax;
+  ip[3] = w->terrain_lam; ip[4] = w->cave_lam; ip[5] = w->nbox;
+  dp[0] = w->amp; dp[1] = w->cave_tau;
+  *boxes = w->boxes;
 }
 
 SG_EXPORT int64_t sg_height(const sg_world* w, int64_t x, int64_t y) {

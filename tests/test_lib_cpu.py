@@ -145,3 +145,30 @@ def test_camera_frame_matches_oracle():
         assert fl.G == fo.G
         n_ok += 1
     assert n_ok > 150
+
+
+def test_gpu_scene_generator_host_contract():
+    """The GPU copy of the terrain generator loads and exports its two entry
+    points; the world parameters it is given decode to the host world's boxes;
+    its workspace is the stated layout (int32 column heights, then the two
+    cave lattice tables of doubles, each 256-byte aligned); bad arguments are
+    refused before anything reaches a device.  Its bytes are compared with the
+    host generator's on the GPU."""
+    sw = scenes.SceneWorld("map1024", 2025)
+    ip, dp, boxes = sw._terrain_params()
+    assert list(ip) == [1, 512, 1024, 512, 64, sw.nbox] and list(dp) == [400.0, 0.6803]
+    X = sw.extent[0]
+    assert boxes.shape == (sw.nbox, 8) and (boxes[:, 7] == 0).all()
+    assert ((boxes[:, 6] >= 9) & (boxes[:, 6] <= 15)).all()
+    assert (boxes[:, 0] >= 0).all() and (boxes[:, 3] <= X).all() and (boxes[:, 3] > boxes[:, 0]).all()
+    assert (boxes[:, 2] >= 0).all() and (boxes[:, 5] <= 1024).all() and (boxes[:, 5] >= boxes[:, 2]).all()
+    L = scenes._gpu_lib()
+    a256 = lambda v: (v + 255) // 256 * 256
+    # cave octaves: wavelengths 64 and 32, lattice ((S-1) >> log2(lam)) + 3 per axis
+    assert L.sgg_work_bytes(ip, dp, 10) == a256(4 << 20) + a256(8 * 18 ** 3) + a256(8 * 34 ** 3)
+    ipn = (ctypes.c_int64 * 6)(*ip)
+    ipn[0] = 0  # not a terrain world
+    assert L.sgg_work_bytes(ipn, dp, 10) == 0
+    assert L.sgg_gen_chunk(ipn, dp, 1, 10, 0, 0, 0, None, 0, None, None, 0, None) == -1
+    assert L.sgg_gen_chunk(ip, dp, 1, 10, 0, 0, 0, None, 0, None, None, 0, None) == -1
+    assert L.sgg_gen_chunk(ip, dp, 1, 11, 0, 0, 0, None, 0, None, None, 0, None) == -1
