@@ -157,6 +157,71 @@ def test_map512_full_frames(env, map512):
     assert len(lods_seen) >= 2
 
 
+def test_map1024_region_full_frame(env):
+    """The 32x32-chunk map of 1024^3 chunks at 2560x1440 (the bench's view 0
+    of it): the 7x7 chunks around the camera hold the map's content and every
+    other chunk is empty (an empty blob in the library's world, no DAG in the
+    oracle's).  Every pixel is compared with the oracle: chunk edge 1024
+    with LODs 1 to 3 picked (7, 6 and 5 internal DAG levels; LOD 0 would need
+    the camera within 256 voxels of a chunk centre, and the single 1024^3
+    terrain chunk covers it)."""
+    svdag, torch = env
+    sw = scenes.SceneWorld("map1024", 2025)
+    CL, S, (gx, gy, gz) = sw.chunk_log2, sw.S, sw.grid
+    thr = (256, 1024, 4096)
+    cam = sw.views(1, 1)[0]
+    ccx, ccy = int(cam.pos[0]) // S, int(cam.pos[1]) // S
+    region = [(cx, cy, 0) for cy in range(max(0, ccy - 3), min(gy, ccy + 4))
+              for cx in range(max(0, ccx - 3), min(gx, ccx + 4))]
+    ow = oracle.World(CL, sw.grid, 4)
+    fr = oracle.camera_frame(cam)
+    lods = ow.lod_pick(fr.O, thr)
+    dev = torch.empty(S ** 3, dtype=torch.uint8, device="cuda")
+    work_dev = None
+    blobs = {}
+
+    def build(c, g):
+        ci = c[0] + gx * c[1]
+        k = int(lods[ci])
+        b = svdag.svd_chunk_build(g, CL, 4)
+        pyr = oracle.pyramid(g, S, k + 1)
+        return c, ci, b, k, oracle.Dag(pyr[k], S >> k)
+
+    t0 = time.time()
+    with ThreadPoolExecutor(NT) as ex:
+        for i in range(0, len(region), NT):
+            futs = []
+            for c in region[i:i + NT]:
+                work_dev = sw.chunk_device(c, dev, work_dev)
+                futs.append(ex.submit(build, c, dev.cpu().numpy()))
+            for f in futs:
+                c, ci, b, k, d = f.result()
+                blobs[c] = b
+                ow.set_dag(ci, k, d)
+    note(f"map1024: {len(region)} chunks around ({ccx}, {ccy}) built in {time.time() - t0:.1f}s")
+    empty = svdag.svd_chunk_build(np.zeros(S ** 3, np.uint8), CL, 4)
+    nbytes = lambda b: sum((svdag.svd_blob_stats_get(b, k)["device_bytes"] + 255) // 256 * 256 for k in range(4))
+    nch = gx * gy * gz
+    pool = torch.empty(svdag.table_bytes(sw.grid) + sum(nbytes(b) for b in blobs.values())
+                       + nch * (nbytes(empty) + 256), dtype=torch.uint8, device="cuda")
+    w = svdag.svd_world_create(svdag.make_desc(CL, sw.grid, 4, thr), pool)
+    for cy in range(gy):
+        for cx in range(gx):
+            svdag.svd_chunk_upload(w, (cx, cy, 0), blobs.get((cx, cy, 0), empty))
+    torch.cuda.synchronize()
+    raw, vt = _trace_like_bench(svdag, torch, w, cam)
+    assert np.array_equal(vt & 3, lods)
+    _properties(svdag, raw, vt, sw)
+    t0 = time.time()
+    ref = ow.trace_frame(lods, fr, mode=1, threads=NT)
+    note(f"map1024 region: oracle {ref.size} rays in {time.time() - t0:.1f}s")
+    compare(svdag, raw, ref, label="map1024 region view 0")
+    seen = set(ref["lod"][ref["hit"] == 1].tolist())
+    assert {int(lods[c[0] + gx * c[1]]) for c in region} == {1, 2, 3}
+    assert len(seen) >= 2, seen
+    del pool
+
+
 def test_map512_beam_pass_changes_no_record(env, map512):
     """The exact beam pass on full 1440p map views: every record equals the
     plain trace's (which the test above checks against the oracle)."""
