@@ -216,6 +216,17 @@ class SceneWorld:
             self._tp = (ip, dp, boxes)
         return self._tp
 
+    def chunk_boxes(self, c) -> np.ndarray:
+        """The boxes that meet chunk c, in paint order, as int32 rows {x0, y0,
+        z0, x1, y1, z1, material, 0}."""
+        boxes = self._terrain_params()[2]
+        S = self.S
+        keep = np.ones(len(boxes), bool)
+        for a in range(3):
+            lo = int(c[a]) * S
+            keep &= (boxes[:, a] < lo + S) & (boxes[:, a + 3] > lo)
+        return np.ascontiguousarray(boxes[keep])
+
     def chunk_device(self, c, out, work=None, stream=None):
         """Generate chunk c on the GPU into `out`, a contiguous uint8 device
         tensor of S^3 bytes: the same bytes as chunk(c).  Terrain kinds only
@@ -232,11 +243,7 @@ class SceneWorld:
             raise ValueError(f"chunk {c} out of range")
         if not (out.is_cuda and out.dtype == torch.uint8 and out.is_contiguous() and out.numel() == S ** 3):
             raise ValueError("out must be a contiguous uint8 device tensor of S^3 bytes")
-        lo = [int(c[a]) * S for a in range(3)]
-        keep = np.ones(len(boxes), bool)
-        for a in range(3):
-            keep &= (boxes[:, a] < lo[a] + S) & (boxes[:, a + 3] > lo[a])
-        sel = np.ascontiguousarray(boxes[keep])
+        sel = self.chunk_boxes(c)
         s = stream if stream is not None else torch.cuda.current_stream(out.device)
         need = int(L.sgg_work_bytes(ip, dp, cl))
         if need == 0:

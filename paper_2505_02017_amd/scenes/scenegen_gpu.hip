@@ -17,30 +17,30 @@
 
 namespace sgg {
 
-__device__ inline uint64_t splitmix64(uint64_t x) {
+__host__ __device__ inline uint64_t splitmix64(uint64_t x) {
   x += 0x9E3779B97F4A7C15ull;
   x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
   x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
   return x ^ (x >> 31);
 }
 
-__device__ inline double lattice(uint64_t seed, int64_t i, int64_t j, int64_t k) {
+__host__ __device__ inline double lattice(uint64_t seed, int64_t i, int64_t j, int64_t k) {
   uint64_t h = splitmix64(seed ^ (uint64_t)i);
   h = splitmix64(h ^ (uint64_t)j);
   h = splitmix64(h ^ (uint64_t)k);
   return (double)(h >> 11) * 0x1p-53;
 }
 
-__device__ inline double fade(double t) { return t * t * (3.0 - 2.0 * t); }
-__device__ inline double lerp(double a, double b, double t) { return a + (b - a) * t; }
+__host__ __device__ inline double fade(double t) { return t * t * (3.0 - 2.0 * t); }
+__host__ __device__ inline double lerp(double a, double b, double t) { return a + (b - a) * t; }
 
-__device__ inline int64_t floordiv(int64_t a, int64_t b) {
+__host__ __device__ inline int64_t floordiv(int64_t a, int64_t b) {
   int64_t q = a / b;
   if ((a % b != 0) && ((a < 0) != (b < 0))) q--;
   return q;
 }
 
-__device__ inline int ilog2(int64_t v) {
+__host__ __device__ inline int ilog2(int64_t v) {
   int l = 0;
   while (((int64_t)1 << (l + 1)) <= v) l++;
   return l;
@@ -59,7 +59,7 @@ struct Params {
 constexpr int kCaveOctaves = 2;
 constexpr int kTerrainOctaves = 6;
 
-__device__ double vnoise2(uint64_t seed, int64_t x, int64_t y, int64_t lam) {
+__host__ __device__ double vnoise2(uint64_t seed, int64_t x, int64_t y, int64_t lam) {
   const int64_t i = floordiv(x, lam), j = floordiv(y, lam);
   const double fx = fade((double)(x - i * lam) / (double)lam);
   const double fy = fade((double)(y - j * lam) / (double)lam);
@@ -68,7 +68,7 @@ __device__ double vnoise2(uint64_t seed, int64_t x, int64_t y, int64_t lam) {
   return lerp(a, b, fy);
 }
 
-__device__ int64_t terrain_h(const Params& p, int64_t x, int64_t y) {
+__host__ __device__ int64_t terrain_h(const Params& p, int64_t x, int64_t y) {
   double s = 0.0, w = 0.0, amp = 1.0;
   for (int o = 0; o < kTerrainOctaves; o++) {
     s += amp * vnoise2(p.terrain_seed + 0x1000ull * (uint64_t)o, x, y, p.terrain_lam >> o);
@@ -82,26 +82,22 @@ __device__ int64_t terrain_h(const Params& p, int64_t x, int64_t y) {
   return h;
 }
 
-// One thread per column of the chunk.
-__global__ void heights_kernel(Params p, int32_t* hh) {
+// Terrain height of column idx = x + S*y of the chunk.
+__host__ __device__ inline int32_t column_height(const Params& p, int64_t idx) {
   const int64_t S = (int64_t)1 << p.chunk_log2;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= S * S) return;
   const int64_t x = idx & (S - 1), y = idx >> p.chunk_log2;
-  hh[idx] = (int32_t)terrain_h(p, p.X0 + x, p.Y0 + y);
+  return (int32_t)terrain_h(p, p.X0 + x, p.Y0 + y);
 }
 
-// One thread per lattice point of one cave octave.
-__global__ void lattice_kernel(Params p, int o, double* V) {
+// Lattice value idx = a + n*(b + n*c) of cave octave o's table.
+__host__ __device__ inline double lattice_entry(const Params& p, int o, int64_t idx) {
   const int64_t n = p.n[o];
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n * n * n) return;
   const int64_t a = idx % n, b = (idx / n) % n, c = idx / (n * n);
-  V[idx] = lattice(p.cave_seed + 0x1000ull * (uint64_t)o, p.i0[o] + a, p.j0[o] + b, p.k0[o] + c);
+  return lattice(p.cave_seed + 0x1000ull * (uint64_t)o, p.i0[o] + a, p.j0[o] + b, p.k0[o] + c);
 }
 
 // The cave fBm at one voxel, from the tabulated lattice values.
-__device__ double cave(const Params& p, const double* const V[2], int64_t X, int64_t Y, int64_t Z) {
+__host__ __device__ double cave(const Params& p, const double* const V[2], int64_t X, int64_t Y, int64_t Z) {
   double v = 0.0, w = 0.0, amp = 1.0;
   for (int o = 0; o < kCaveOctaves; o++) {
     const int64_t lam = p.cave_lam >> o;
@@ -126,15 +122,14 @@ __device__ double cave(const Params& p, const double* const V[2], int64_t X, int
   return v / w;
 }
 
-// One thread per voxel, x fastest.  boxes: nbox records {x0, y0, z0, x1, y1,
-// z1, material, 0} (half-open bounds), already limited to this chunk, in paint
-// order.
-__global__ void voxel_kernel(Params p, const int32_t* hh, const double* V0, const double* V1,
-                             const int32_t* boxes, uint8_t* out) {
+// Material of voxel idx = x + S*(y + S*z).  hh: the chunk's column heights;
+// V0, V1: the cave octaves' lattice tables; boxes: nbox records {x0, y0, z0,
+// x1, y1, z1, material, 0} (half-open bounds), at least those meeting this
+// chunk, in paint order.
+__host__ __device__ inline uint8_t voxel_value(const Params& p, const int32_t* hh, const double* V0,
+                                               const double* V1, const int32_t* boxes, int64_t idx) {
   const uint32_t cl = p.chunk_log2;
   const int64_t S = (int64_t)1 << cl;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (S << (2 * cl))) return;
   const int64_t x = idx & (S - 1), y = (idx >> cl) & (S - 1), z = idx >> (2 * cl);
   const int64_t X = p.X0 + x, Y = p.Y0 + y, Z = p.Z0 + z;
   const int64_t h = hh[(y << cl) + x];
@@ -150,7 +145,28 @@ __global__ void voxel_kernel(Params p, const int32_t* hh, const double* V0, cons
     const int32_t* r = boxes + 8 * b;
     if (X >= r[0] && X < r[3] && Y >= r[1] && Y < r[4] && Z >= r[2] && Z < r[5]) m = (uint8_t)r[6];
   }
-  out[idx] = m;
+  return m;
+}
+
+// One thread per column of the chunk.
+__global__ void heights_kernel(Params p, int32_t* hh) {
+  const int64_t S = (int64_t)1 << p.chunk_log2;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < S * S) hh[idx] = column_height(p, idx);
+}
+
+// One thread per lattice point of one cave octave.
+__global__ void lattice_kernel(Params p, int o, double* V) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < p.n[o] * p.n[o] * p.n[o]) V[idx] = lattice_entry(p, o, idx);
+}
+
+// One thread per voxel, x fastest.
+__global__ void voxel_kernel(Params p, const int32_t* hh, const double* V0, const double* V1,
+                             const int32_t* boxes, uint8_t* out) {
+  const uint32_t cl = p.chunk_log2;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < ((int64_t)1 << (3 * cl))) out[idx] = voxel_value(p, hh, V0, V1, boxes, idx);
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -158,8 +174,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 void octave_tables(Params& p) {
   const int64_t S = (int64_t)1 << p.chunk_log2;
   for (int o = 0; o < kCaveOctaves; o++) {
-    int sh = 0;
-    while (((int64_t)1 << (sh + 1)) <= (p.cave_lam >> o)) sh++;
+    const int sh = ilog2(p.cave_lam >> o);
     p.n[o] = ((S - 1) >> sh) + 3;
     p.i0[o] = p.X0 >> sh;
     p.j0[o] = p.Y0 >> sh;

@@ -1,8 +1,10 @@
 // Test infrastructure: the library's kernel logic (chunk stage, beam pass,
 // per-pixel trace from kernels.hip) run on the host over the same device
-// images, so CPU-only test runs check it against the oracle.  Not part of
+// images, so CPU-only test runs check it against the oracle; likewise the GPU
+// scene generator's per-element code, checked against the host generator.  Not part of
 // libsvdag; nothing here touches a GPU.
 #include "kernels.hip"
+#include "../paper_2505_02017_amd/scenes/scenegen_gpu.hip"
 
 #include <algorithm>
 #include <cstring>
@@ -154,4 +156,32 @@ extern "C" int hk_beam_cube(const int64_t O[3], const int64_t A[3], const int64_
   if (!beam_cone(bp, x0, y0, x1, y1, q)) return -1;
   *dist = beam_dist(q, lo, s);
   return beam_outside(q, lo, s) ? 1 : 0;
+}
+
+// The GPU scene generator's element functions (column heights, cave lattice
+// tables, voxels) run on the host over one chunk; arguments as sgg_gen_chunk,
+// with host memory.  Returns 0, or -1 on bad arguments.
+extern "C" int hk_scene_chunk(const int64_t ip[6], const double dp[2], uint64_t seed, uint32_t chunk_log2,
+                              uint32_t cx, uint32_t cy, uint32_t cz, const int32_t* boxes, uint32_t nbox,
+                              uint8_t* out, int threads) {
+  sgg::Params p{};
+  if (!sgg::params_from(p, ip, dp, seed, chunk_log2, cx, cy, cz, nbox)) return -1;
+  const int64_t S = (int64_t)1 << chunk_log2;
+  std::vector<int32_t> hh((size_t)(S * S));
+  for (int64_t i = 0; i < S * S; i++) hh[(size_t)i] = sgg::column_height(p, i);
+  std::vector<double> V[sgg::kCaveOctaves];
+  for (int o = 0; o < sgg::kCaveOctaves; o++) {
+    V[o].resize((size_t)(p.n[o] * p.n[o] * p.n[o]));
+    for (size_t i = 0; i < V[o].size(); i++) V[o][i] = sgg::lattice_entry(p, o, (int64_t)i);
+  }
+  const int nt = std::max(1, std::min(threads, (int)S));
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; t++)
+    th.emplace_back([&, t] {
+      for (int64_t z = S * t / nt; z < S * (t + 1) / nt; z++)
+        for (int64_t i = z * S * S; i < (z + 1) * S * S; i++)
+          out[i] = sgg::voxel_value(p, hh.data(), V[0].data(), V[1].data(), boxes, i);
+    });
+  for (auto& x : th) x.join();
+  return 0;
 }

@@ -50,6 +50,9 @@ def lib():
         L.hk_trace.argtypes = [vp, vp, u32, vp, vp, u32]
         L.hk_beam_cube.argtypes = [vp, vp, vp, vp, u32, u32, u32, u32, vp, ctypes.c_int32, vp]
         L.hk_beam_cube.restype = ctypes.c_int
+        L.hk_scene_chunk.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.c_uint64, u32, u32, u32, u32, vp, u32, vp, ctypes.c_int]
+        L.hk_scene_chunk.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -88,3 +91,16 @@ def beam_cube(O, A, BX, BY, tile, lo, s):
     r = lib().hk_beam_cube(i64(*O), i64(*A), i64(*BX), i64(*BY), *tile, (ctypes.c_int32 * 3)(*lo), s,
                            ctypes.byref(d))
     return (None if r < 0 else bool(r)), d.value
+
+
+def scene_chunk(sw, c, threads=8):
+    """Chunk c of terrain world `sw` from the GPU generator's element code run
+    on the host."""
+    ip, dp, _ = sw._terrain_params()
+    sel = sw.chunk_boxes(c)
+    boxes = sel if len(sel) else np.zeros((1, 8), np.int32)
+    out = np.empty(sw.S ** 3, np.uint8)
+    rc = lib().hk_scene_chunk(ip, dp, ctypes.c_uint64(sw.seed), sw.chunk_log2, int(c[0]), int(c[1]), int(c[2]),
+                              boxes.ctypes.data, len(sel), out.ctypes.data, threads)
+    assert rc == 0, rc
+    return out

@@ -92,3 +92,24 @@ def test_terrain_views_beam_cull_and_not_loaded(env):
             assert np.all(nl[hit_in_half]), f"view {v}: a ray read a chunk that is not loaded"
             marked += int(nl.sum())
     assert marked > 0
+
+
+def test_gpu_scene_generator_code_equals_host_generator(env):
+    """The GPU scene generator's per-element code (scenegen_gpu.hip: column
+    heights, cave lattice tables, voxels), run on the host, against the host
+    generator byte for byte: worlds with several z layers, chunk edges below
+    the cave wavelength, and map512 chunks where boxes meet."""
+    _, hk = env
+    cases = [(scenes.SceneWorld("custom", 7, chunk_log2=5, grid=(2, 2, 2)), None),
+             (scenes.SceneWorld("custom", 3, chunk_log2=3, grid=(4, 4, 2)), [(0, 0, 0), (3, 2, 1), (1, 3, 0)]),
+             (scenes.SceneWorld("custom", 11, chunk_log2=6, grid=(3, 2, 1)), None),
+             (scenes.SceneWorld("map512", 2025), [(3, 5, 0), (15, 15, 0)])]
+    nboxes = 0
+    for sw, chunks in cases:
+        for c in (chunks or list(sw.chunks())):
+            nboxes += len(sw.chunk_boxes(c))
+            a = sw.chunk(c, threads=NT)
+            b = hk.scene_chunk(sw, c, threads=NT)
+            bad = np.flatnonzero(a != b)
+            assert bad.size == 0, f"{sw.kind} {c}: {bad.size} bytes differ"
+    assert nboxes > 10
