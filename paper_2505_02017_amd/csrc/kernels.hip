@@ -310,6 +310,18 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
       }
       k = (int)(v & kViewLodMask);
       const DevDag* dag = &p.desc[(size_t)ci * 4 + k];
+      // Every solid cell of the chunk lies in its tight box.  Cell
+      // coordinates of the mirrored ray never decrease, so a ray already at
+      // or past the box's upper face on some axis meets none of them: cross
+      // the chunk as an empty one.  (A face behind the origin wraps to a
+      // numerator near 2^32; the test may then read it as not passed, which
+      // only forgoes the skip.)
+      bool beyond = false;
+      _Pragma("unroll") for (int a = 0; a < 3; a++) {
+        const uint32_t b = r.cls(a) ? (1u << (CL - k)) - dag->lo[a] : dag->hi[a] + 1u;
+        beyond |= r.past_n(a, ((((uint32_t)c[a] << (CL - k)) + b) << (k + 16)) - r.Oml[a]);
+      }
+      if (!beyond) {
       nodes = (gptr32)dag->nodes;
       leaves = (gptr64)dag->leaves;
       const uint32_t root = dag->root;
@@ -365,8 +377,10 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
         }
       }
       continue;
+      }
     }
-    // an empty or culled chunk: cross it
+    // an empty or culled chunk, or one whose solid cells all lie behind the
+    // ray: cross it
     uint32_t diff;
     if (!exit_cell(r, E, c, diff)) { status = kMiss; break; }
     _Pragma("unroll") for (int a = 0; a < 3; a++) E[a] = ((uint32_t)(c[a] + 1) << (CL + 16)) - r.Oml[a];
