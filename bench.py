@@ -389,8 +389,9 @@ def main():
             if "valu_lane_utilisation" in prof:
                 result["valu_issue"]["lane_utilisation"] = float(prof["valu_lane_utilisation"])
         # ---- CPU baseline: the oracle (as is) on a bounded sample: whole views
-        #      in benchmark order while the time budget lasts, else evenly
-        #      spaced pixels of view 0
+        #      in benchmark order while the time budget lasts (repeated passes
+        #      over all of them if they fit more than once, at most 8), else
+        #      evenly spaced pixels of view 0
         pilot = np.arange(0, W * H, max(1, (W * H) // 4000), dtype=np.uint32)
         t = time.perf_counter()
         ow.trace_frame(view_lods[0], frames[0], pilot, mode=1, threads=args.threads)
@@ -400,10 +401,16 @@ def main():
         n0 = W * H if n_budget >= W * H else n_budget
         sample0 = np.linspace(0, W * H - 1, n0).astype(np.uint32)
         t = time.perf_counter()
-        refs = [ow.trace_frame(view_lods[v], frames[v], sample0 if v == 0 else None, mode=1,
-                               threads=args.threads) for v in range(nviews_cpu)]
-        dt = time.perf_counter() - t
-        n = n0 + (nviews_cpu - 1) * W * H
+        passes = 0
+        while True:
+            refs = [ow.trace_frame(view_lods[v], frames[v], sample0 if v == 0 else None, mode=1,
+                                   threads=args.threads) for v in range(nviews_cpu)]
+            passes += 1
+            dt = time.perf_counter() - t
+            # another pass over all views only if it still fits the budget
+            if nviews_cpu < nviews or passes >= 8 or dt * (passes + 1) / passes > args.cpu_seconds:
+                break
+        n = passes * (n0 + (nviews_cpu - 1) * W * H)
         # view 0 of the sample doubles as a parity spot-check of the benchmarked path
         step(0)
         torch.cuda.synchronize()
@@ -414,6 +421,8 @@ def main():
             for f in ("hit", "x", "y", "z", "lod", "face", "material")))
         what = (f"all pixels of views 0..{nviews_cpu - 1}" if n0 == W * H
                 else f"{n0} evenly spaced pixels of view 0")
+        if passes > 1:
+            what += f", {passes} passes"
         result["cpu_baseline"] = {
             "value": round(n / dt / 1e9, 6), "unit": "Grays/s", "cores": args.threads,
             "kind": "oracle",
