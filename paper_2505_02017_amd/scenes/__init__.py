@@ -250,12 +250,13 @@ class SceneWorld:
             raise ValueError("bad generator parameters")
         if work is None or work.numel() < need:
             work = torch.empty(need, dtype=torch.uint8, device=out.device)
-        bd = torch.from_numpy(sel if len(sel) else np.zeros((1, 8), np.int32)).to(out.device)
-        with torch.cuda.stream(s):
+        with torch.cuda.stream(s):  # the box list's copy is ordered before the kernels that read it
+            bd = torch.from_numpy(sel if len(sel) else np.zeros((1, 8), np.int32)).to(out.device)
             rc = L.sgg_gen_chunk(ip, dp, ctypes.c_uint64(self.seed), cl, int(c[0]), int(c[1]), int(c[2]),
                                  bd.data_ptr(), len(sel), out.data_ptr(), work.data_ptr(), work.numel(),
                                  ctypes.c_void_p(s.cuda_stream))
         bd.record_stream(s)
+        work.record_stream(s)  # held until the stream has run the generation, even if dropped
         if rc != 0:
             raise RuntimeError(f"sgg_gen_chunk failed ({rc})")
         return work
