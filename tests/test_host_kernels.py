@@ -113,3 +113,43 @@ def test_gpu_scene_generator_code_equals_host_generator(env):
             bad = np.flatnonzero(a != b)
             assert bad.size == 0, f"{sw.kind} {c}: {bad.size} bytes differ"
     assert nboxes > 10
+
+
+@pytest.mark.parametrize("cfg", [
+    (4, (3, 3, 2), 2, (10, 0, 0)),
+    (5, (2, 3, 1), 3, (16, 40, 0)),
+])
+def test_small_tight_boxes_adversarial(env, cfg):
+    """Chunks holding one small solid block each (or nothing), so that their
+    tight boxes are much smaller than the chunks and the trace often crosses
+    a chunk because the ray is already past its box: the adversarial ray
+    families (integer and half-voxel origins, rays lying in grid planes,
+    through edges and corners, all direction signs) against the oracle."""
+    svdag, hk = env
+    chunk_log2, grid, lod_count, thr = cfg
+    rng = np.random.default_rng(chunk_log2 * 100 + lod_count)
+    S = 1 << chunk_log2
+    nch = grid[0] * grid[1] * grid[2]
+    dense = {}
+    for ci in range(nch):
+        g = np.zeros((S, S, S), np.uint8)  # indexed [z, y, x]
+        if rng.random() < 0.85:
+            lo = rng.integers(0, S - 1, 3)
+            hi = np.minimum(lo + rng.integers(1, S // 2 + 1, 3), S)
+            g[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = rng.integers(1, 16, (hi[2] - lo[2], hi[1] - lo[1],
+                                                                              hi[0] - lo[0]), dtype=np.uint8)
+        dense[ci] = g.reshape(-1)
+    blobs = {ci: svdag.svd_chunk_build(g, chunk_log2, lod_count) for ci, g in dense.items()}
+    hw = hk.HostWorld(svdag, chunk_log2, grid, lod_count, thr, blobs)
+    ow = oracle.World(chunk_log2, grid, lod_count)
+    for ci, g in dense.items():
+        ow.add_chunk(ci, g)
+    ext = [g * S for g in grid]
+    hits = 0
+    for i, (O, A, BX, BY, W, H) in enumerate(gp._frames(rng, ext, 200, 16, 8)):
+        fr = svdag.make_frame(O, A, BX, BY, W, H)
+        raw, view = hw.trace(fr, threads=NT)
+        lods = ow.lod_pick(np.array(O, np.int64), thr)
+        ref = ow.trace_frame(lods, gp._oracle_frame(fr), mode=1, threads=NT)
+        hits += compare(svdag, raw, ref, label=f"{cfg} frame {i}")
+    assert hits > 0
