@@ -17,6 +17,11 @@ Prints one JSON line (rank 0).  Besides the throughput it reports:
   valu_issue    the trace kernel's VALU instructions (counters) per second
                 against the issue peak, and its lane utilisation;
   cpu_baseline  the CPU oracle timed on a bounded sample of the same views.
+
+Other workloads: --workload terrain1024 | noise64 | map1024.  map1024 (32x32
+chunks of 1024^3) is generated on the GPU with --gen gpu (the same bytes as
+the host generator) and runs with --no-cpu-baseline, since the oracle cannot
+build all of its chunks within the run.
 """
 from __future__ import annotations
 
