@@ -289,6 +289,28 @@ int svd_batch_trace(svd_batch* b, const svd_camera* cams, uint32_t n, svd_hit* o
 int svd_batch_trace_frames(svd_batch* b, const svd_ray_frame* frames, uint32_t n, svd_hit* out_dev,
                            uint64_t out_records, uint32_t flags, void* stream);
 
+/* Allocation-free form of svd_batch_trace_frames, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  No batch object is needed, and the call
+ * allocates nothing (no device or pinned memory, stream, event, graph or
+ * host heap).  The queue block, batch header, views and per-(view, chunk)
+ * view tables of the call live in one static device array of the library,
+ * 1 MiB per GPU, held by each GPU the library runs on until the process
+ * ends; the views reach it as kernel arguments.  The kernels (view writes,
+ * queue clear, stage, beam with SVD_BEAM, persistent trace with 16x4-pixel
+ * tiles) are enqueued on `stream`, and can be captured into a graph.
+ *   Layout and capacity: 2304 + 256*n + 4*n*nchunks (rounded up to 256)
+ *   bytes must fit 1 MiB (SVD_ENOMEM otherwise, before anything is
+ *   enqueued); n <= 65535.  Output and errors otherwise as
+ *   svd_batch_trace_frames.
+ * The array is shared by every call on the same GPU and keeps the last
+ * call's contents (the queue counters are cleared by each call): calls that
+ * overlap on one GPU (different streams, or other threads) race and must be
+ * serialised by the caller.  The first call on a device also looks up the
+ * array's address there (once per device). */
+int svd_batch_trace_frames_static(svd_world* w, const svd_ray_frame* frames, uint32_t n, svd_hit* out_dev,
+                                  uint64_t out_records, uint32_t flags, void* stream);
+
 /* Work shape of the persistent trace: a wave's tile is tile_w x (64/tile_w)
  * pixels (tile_w in {8, 16, 32, 64}); a wave takes `claim` (1..16)
  * consecutive tiles per queue access.  Results do not depend on it. */

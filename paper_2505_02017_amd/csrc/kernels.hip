@@ -27,6 +27,9 @@
 // Hits are resolved after the loop (DFS index, material run, t, face).
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+#include <mutex>
+
 #include "svdag_internal.h"
 
 namespace svd {
@@ -878,6 +881,83 @@ int launch_batch(const BatchParams& p, uint32_t trace_blocks, void* stream) {
   hipLaunchKernelGGL(batch_trace_kernel, dim3(trace_blocks), dim3(kBlock), 0, s, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return svd_fail(SVD_EDEVICE, "batch launch: %s", hipGetErrorString(e));
+  return SVD_OK;
+}
+
+int launch_batch_direct(const BatchParams& p, uint32_t views, uint32_t trace_blocks, bool beam, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, p.queue);
+  hipLaunchKernelGGL(batch_stage_kernel, dim3((p.nchunks + 63) / 64, views), dim3(64), 0, s, p);
+  if (beam) hipLaunchKernelGGL(batch_beam_kernel, dim3(trace_blocks * 8), dim3(kBeamBlock), 0, s, p);
+  hipLaunchKernelGGL(batch_trace_kernel, dim3(trace_blocks), dim3(kBlock), 0, s, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return svd_fail(SVD_EDEVICE, "batch launch: %s", hipGetErrorString(e));
+  return SVD_OK;
+}
+
+// ------------------------------------------------------ allocation-free batch
+// Batch area of svd_batch_trace_frames_static (queue block, header, views,
+// per-(view, chunk) tables), kStaticScratchBytes per GPU, held until the
+// process ends.  In host code `scratch` names a host-side stand-in, not
+// device memory: host code only ever uses the device address that
+// hipGetSymbolAddress returns for the current device (static_device).
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+int static_device(StaticDevice* out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static StaticDevice dev_state[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return svd_fail(SVD_EDEVICE, "static batch: hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return svd_fail(SVD_EDEVICE, "static batch: device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(mu);
+  StaticDevice& d = dev_state[dev];
+  if (!d.scratch) {
+    uint8_t* ptr = nullptr;
+    e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return svd_fail(SVD_EDEVICE, "static batch: hipGetSymbolAddress: %s", hipGetErrorString(e));
+    int cus = 0, n = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess || cus < 1) return svd_fail(SVD_EDEVICE, "static batch: cannot query the device");
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_trace_kernel, kBlock, 0);
+    if (e != hipSuccess || n < 1) return svd_fail(SVD_EDEVICE, "static batch: occupancy query failed");
+    d.cus = (uint32_t)cus;
+    d.per_cu = (uint32_t)n;
+    d.scratch = ptr;  // set last: a set-up that failed is retried on the next call
+  }
+  *out = d;
+  return SVD_OK;
+}
+
+// Views travel as kernel arguments, so no host staging buffer (and no copy
+// from host memory) is needed; a block copies them word by word.
+struct ViewPack {
+  uint32_t hdr[sizeof(BatchHeader) / 4];
+  uint32_t count, with_hdr, pad[2];
+  uint32_t words[kPackViews * (sizeof(BatchView) / 4)];
+};
+
+__global__ __launch_bounds__(256) void set_views_kernel(uint32_t* dst, uint32_t* hdr_dst, ViewPack pk) {
+  const uint32_t t = threadIdx.x, n = pk.count * (uint32_t)(sizeof(BatchView) / 4);
+  for (uint32_t i = t; i < n; i += 256) dst[i] = pk.words[i];
+  if (pk.with_hdr && t < sizeof(BatchHeader) / 4) hdr_dst[t] = pk.hdr[t];
+}
+
+int launch_set_views(BatchView* dst, const BatchView* src, uint32_t count, BatchHeader* hdr_dst,
+                     const BatchHeader* hdr, void* stream) {
+  if (count > kPackViews) return svd_fail(SVD_EINVAL, "internal: view pack > %u", kPackViews);
+  ViewPack pk;
+  memset(&pk, 0, sizeof(pk));
+  if (hdr) memcpy(pk.hdr, hdr, sizeof(BatchHeader));
+  pk.count = count;
+  pk.with_hdr = hdr != nullptr;
+  memcpy(pk.words, src, (size_t)count * sizeof(BatchView));
+  hipLaunchKernelGGL(set_views_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, reinterpret_cast<uint32_t*>(dst),
+                     reinterpret_cast<uint32_t*>(hdr_dst), pk);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return svd_fail(SVD_EDEVICE, "view pack launch: %s", hipGetErrorString(e));
   return SVD_OK;
 }
 

@@ -849,3 +849,85 @@ extern "C" int svd_batch_tune(svd_batch* b, const svd_camera* cams, uint32_t n, 
   if (best_ms) *best_ms = best;
   return rc;
 }
+
+// ------------------------------------------------- allocation-free batches
+// svd_batch_trace_frames without a batch object: the queue block, header,
+// views and view tables live in the library's static per-GPU array (laid out
+// like a batch's pool area), the views reach it as kernel arguments, and the
+// kernels run directly on the caller's stream.  Nothing is allocated: no
+// device or pinned memory, no stream, event or graph, no host heap.
+extern "C" int svd_batch_trace_frames_static(svd_world* w, const svd_ray_frame* frames, uint32_t n,
+                                             svd_hit* out_dev, uint64_t out_records, uint32_t flags,
+                                             void* stream) {
+  if (!w || !frames || !out_dev || n == 0) return svd_fail(SVD_EINVAL, "svd_batch_trace_frames_static: bad argument");
+  if (flags & ~(SVD_NO_CULL | SVD_BEAM)) return svd_fail(SVD_EINVAL, "static batch: unknown flags");
+  if (w->absent) return svd_fail(SVD_ENOTFOUND, "static batch: %u (chunk, LOD) slots were never uploaded", w->absent);
+  const size_t tables = ((size_t)n * w->nchunks * 4 + 255) / 256 * 256;
+  const size_t need = kQueueBlockBytes + 256 + (size_t)n * sizeof(BatchView) + tables;
+  if (n > 65535 || need > kStaticScratchBytes)
+    return svd_fail(SVD_ENOMEM, "static batch: %u views over %u chunks need %zu bytes of scratch; the limit is %zu",
+                    n, w->nchunks, need, kStaticScratchBytes);
+  constexpr uint32_t tw = kViewTileW, th = 64 / kViewTileW;
+  uint64_t tiles = 0, px_total = 0;
+  for (uint32_t v = 0; v < n; v++) {
+    const int rc = check_frame(&frames[v]);
+    if (rc) return rc;
+    tiles += (uint64_t)((frames[v].width + tw - 1) / tw) * ((frames[v].height + th - 1) / th);
+    px_total += (uint64_t)frames[v].width * frames[v].height;
+  }
+  if (tiles >= (1ull << 31)) return svd_fail(SVD_EINVAL, "static batch: too many tiles");
+  if (px_total > out_records)
+    return svd_fail(SVD_EINVAL, "static batch: output holds %llu records, views need %llu",
+                    (unsigned long long)out_records, (unsigned long long)px_total);
+  StaticDevice dev;
+  int rc = static_device(&dev);
+  if (rc) return rc;
+  BatchParams p;
+  memset(&p, 0, sizeof(p));
+  p.queue = (uint32_t*)dev.scratch;
+  p.hdr = (BatchHeader*)(dev.scratch + kQueueBlockBytes);
+  BatchView* d_views = (BatchView*)(dev.scratch + kQueueBlockBytes + 256);
+  p.views = d_views;
+  p.view_tables = (uint32_t*)(dev.scratch + kQueueBlockBytes + 256 + (size_t)n * sizeof(BatchView));
+  p.max_views = n;
+  memcpy(p.grid, w->desc.grid, sizeof(p.grid));
+  p.chunk_log2 = w->desc.chunk_log2;
+  p.lod_count = w->desc.lod_count;
+  memcpy(p.thr, w->desc.lod_threshold, sizeof(p.thr));
+  p.nchunks = w->nchunks;
+  p.desc = w->d_desc;
+  BatchHeader h;
+  memset(&h, 0, sizeof(h));
+  h.nviews = n;
+  h.total_tiles = (uint32_t)tiles;
+  h.tile_w = tw;
+  h.claim = 1;
+  h.beam = (flags & SVD_BEAM) != 0;
+  BatchView pack[kPackViews];
+  uint32_t tbase = 0;
+  uint64_t rec = 0;
+  for (uint32_t v0 = 0; v0 < n; v0 += kPackViews) {
+    const uint32_t cnt = std::min(kPackViews, n - v0);
+    for (uint32_t i = 0; i < cnt; i++) {
+      const svd_ray_frame& f = frames[v0 + i];
+      BatchView& bv = pack[i];
+      memset(&bv, 0, sizeof(bv));
+      memcpy(bv.O, f.O, sizeof(bv.O));
+      memcpy(bv.A, f.A, sizeof(bv.A));
+      memcpy(bv.BX, f.BX, sizeof(bv.BX));
+      memcpy(bv.BY, f.BY, sizeof(bv.BY));
+      bv.cull = !(flags & SVD_NO_CULL) && cull_planes(&f, bv.n);
+      bv.out = (uint64_t)(uintptr_t)(out_dev + rec);
+      bv.W = f.width;
+      bv.H = f.height;
+      bv.tiles_x = (f.width + tw - 1) / tw;
+      bv.tile_base = tbase;
+      tbase += bv.tiles_x * ((f.height + th - 1) / th);
+      rec += (uint64_t)f.width * f.height;
+    }
+    rc = launch_set_views(d_views + v0, pack, cnt, v0 == 0 ? p.hdr : nullptr, v0 == 0 ? &h : nullptr, stream);
+    if (rc) return rc;
+  }
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>((uint64_t)dev.per_cu * dev.cus, (tiles + 3) / 4);
+  return launch_batch_direct(p, n, blocks, (flags & SVD_BEAM) != 0, stream);
+}

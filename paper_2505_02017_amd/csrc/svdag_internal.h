@@ -182,6 +182,27 @@ int batch_trace_occupancy(uint32_t* blocks_per_cu);
 // then starts from zero and clears it again when it ends)
 int launch_queue_clear(uint32_t* queue, void* stream);
 
+// Allocation-free batches (svd_batch_trace_frames_static): one file-scope
+// device array per GPU holds a call's queue block, header, views and view
+// tables, laid out as a batch's pool area.
+constexpr size_t kStaticScratchBytes = (size_t)1 << 20;
+struct StaticDevice {
+  uint8_t* scratch;  // device address of this GPU's copy of the array
+  uint32_t cus;      // compute units
+  uint32_t per_cu;   // batch trace blocks that fit a CU
+};
+// Set-up of the current device on its first use (symbol address, CU count,
+// occupancy), cached per device afterwards.
+int static_device(StaticDevice* out);
+// Write views[first, first + count) (count <= kPackViews) and, when hdr is
+// not null, the header, by a kernel whose arguments carry them.
+constexpr uint32_t kPackViews = 8;
+int launch_set_views(BatchView* dst, const BatchView* src, uint32_t count, BatchHeader* hdr_dst,
+                     const BatchHeader* hdr, void* stream);
+// The batch kernels (queue reset, stage, beam when `beam`, trace) with
+// `trace_blocks` persistent trace blocks, outside any graph.
+int launch_batch_direct(const BatchParams& p, uint32_t views, uint32_t trace_blocks, bool beam, void* stream);
+
 }  // namespace svd
 
 struct svd_blob {

@@ -40,7 +40,7 @@ EXPORTS = [
     "svd_batch_create", "svd_batch_destroy", "svd_batch_trace", "svd_batch_trace_frames",
     "svd_batch_set_tiling", "svd_batch_set_occupancy", "svd_batch_get_tiling", "svd_batch_tune",
     "svd_server_create", "svd_server_set_chunk", "svd_server_submit", "svd_server_poll",
-    "svd_server_stats_get", "svd_server_destroy",
+    "svd_server_stats_get", "svd_server_destroy", "svd_batch_trace_frames_static",
 ]
 
 
@@ -148,6 +148,7 @@ def lib() -> ctypes.CDLL:
         L.svd_batch_get_tiling.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32)]
         L.svd_batch_tune.argtypes = [vp, ctypes.POINTER(svd_camera), u32, vp, u64, u32, vp,
                                      ctypes.POINTER(ctypes.c_float)]
+        L.svd_batch_trace_frames_static.argtypes = [vp, ctypes.POINTER(svd_ray_frame), u32, vp, u64, u32, vp]
         L.svd_server_create.argtypes = [vp, ctypes.POINTER(svd_server_desc), ctypes.POINTER(vp)]
         L.svd_server_set_chunk.argtypes = [vp, ctypes.POINTER(u32), vp]
         L.svd_server_submit.argtypes = [vp, ctypes.POINTER(svd_camera), vp, u32, u64]
@@ -474,6 +475,14 @@ def svd_batch_trace_frames(b: Batch, frames, out, flags: int = 0, stream=None):
     arr = (svd_ray_frame * len(frames))(*frames)
     ptr, cap = _batch_out(out)
     _check(lib().svd_batch_trace_frames(b.ptr, arr, len(frames), ptr, cap, flags, _stream_ptr(stream)))
+
+
+def svd_batch_trace_frames_static(w: World, frames, out, flags: int = 0, stream=None):
+    """Batch of frames without a batch object: nothing is allocated (the
+    library's static per-GPU scratch holds the queue, views and tables)."""
+    arr = (svd_ray_frame * len(frames))(*frames)
+    ptr, cap = _batch_out(out)
+    _check(lib().svd_batch_trace_frames_static(w.ptr, arr, len(frames), ptr, cap, flags, _stream_ptr(stream)))
 
 
 def svd_batch_set_tiling(b: Batch, tile_w: int, claim: int):
