@@ -24,7 +24,8 @@ HIT_DTYPE = np.dtype([
 
 
 COUNT_DTYPE = np.dtype([("chunk_visits", np.int32), ("chunk_entries", np.int32),
-                        ("node_cubes", np.int32), ("leaf_cubes", np.int32)])
+                        ("node_cubes", np.int32), ("leaf_cubes", np.int32),
+                        ("preceding_siblings", np.int32), ("run_probes", np.int32)])
 
 
 class _Frame(ctypes.Structure):

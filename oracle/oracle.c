@@ -450,22 +450,25 @@ static void mark(uint8_t* m, uint32_t i) {
 }
 
 static int dag_lookup(const or_dag* d, uint32_t x, uint32_t y, uint32_t z, uint32_t* dfs,
-                      uint32_t* empty_level, const or_marks* mk);
+                      uint32_t* empty_level, const or_marks* mk, uint32_t* siblings);
 
 /* Point query.  The DFS index is the sum, along the root-to-leaf path, of the
  * subtree counts of the preceding siblings, plus the set bits below the
  * cell's bit in its leaf bitmap (Section 3.3). */
 int or_dag_lookup(const or_dag* d, uint32_t x, uint32_t y, uint32_t z, uint32_t* dfs,
                   uint32_t* empty_level) {
-  return dag_lookup(d, x, y, z, dfs, empty_level, NULL);
+  return dag_lookup(d, x, y, z, dfs, empty_level, NULL, NULL);
 }
 
+/* `siblings` (may be NULL) gets, for a solid cell, the number of preceding
+ * set siblings summed over the internal levels of its path: the subtree
+ * counts that the DFS index adds up (Section 3.3). */
 static int dag_lookup(const or_dag* d, uint32_t x, uint32_t y, uint32_t z, uint32_t* dfs,
-                      uint32_t* empty_level, const or_marks* mk) {
+                      uint32_t* empty_level, const or_marks* mk, uint32_t* siblings) {
   if (d->n_words == 0) { *empty_level = d->root_level; return 0; }
   uint32_t path[16];
   uint32_t np = 0;
-  uint32_t off = 0, acc = 0;
+  uint32_t off = 0, acc = 0, nsib = 0;
   for (uint32_t l = d->root_level; l >= 3; l--) {
     const uint32_t mask = d->words[off];
     const uint32_t s = l - 1;
@@ -478,6 +481,7 @@ static int dag_lookup(const or_dag* d, uint32_t x, uint32_t y, uint32_t z, uint3
       acc += (l > 3) ? d->words[p + 1] : (uint32_t)__builtin_popcountll(d->leaves[p]);
       slot++;
     }
+    nsib += slot;
     const uint32_t ptr = d->words[off + 2 + slot];
     if (mk) {
       mark(mk->words, off + 2 + slot);
@@ -493,6 +497,7 @@ static int dag_lookup(const or_dag* d, uint32_t x, uint32_t y, uint32_t z, uint3
       if (!((bits >> b) & 1)) { *empty_level = 0; return 0; }
       acc += (uint32_t)__builtin_popcountll(bits & ((1ull << b) - 1));
       *dfs = acc;
+      if (siblings) *siblings = nsib;
       /* a hit reads the prefix count of every child on its path, from the
        * root's child down to the leaf (one per internal level) */
       if (mk)
@@ -504,15 +509,18 @@ static int dag_lookup(const or_dag* d, uint32_t x, uint32_t y, uint32_t z, uint3
   return 0; /* not reached: root_level >= 3 */
 }
 
-static uint8_t dag_material(const or_dag* d, uint32_t i, const or_marks* mk);
+static uint8_t dag_material(const or_dag* d, uint32_t i, const or_marks* mk, uint32_t* probes);
 
 /* Material of DFS index i: the run block with the largest start <= i. */
-uint8_t or_dag_material(const or_dag* d, uint32_t i) { return dag_material(d, i, NULL); }
+uint8_t or_dag_material(const or_dag* d, uint32_t i) { return dag_material(d, i, NULL, NULL); }
 
-static uint8_t dag_material(const or_dag* d, uint32_t i, const or_marks* mk) {
+/* `probes` (may be NULL) gets the number of run starts the search compares. */
+static uint8_t dag_material(const or_dag* d, uint32_t i, const or_marks* mk, uint32_t* probes) {
   uint32_t lo = 0, hi = d->n_rle; /* answer in [lo, hi) */
+  if (probes) *probes = 0;
   while (hi - lo > 1) {
     uint32_t mid = lo + (hi - lo) / 2;
+    if (probes) (*probes)++;
     if (mk) mark(mk->rle, mid);
     if (d->rle_start[mid] <= i) lo = mid; else hi = mid;
   }
@@ -692,7 +700,8 @@ typedef struct {
 /* Occupancy of world LOD-k cell c in chunk ci.  Returns 1 if solid (and the
  * material), else 0 with *skip = level (in cells) of an empty cube around it. */
 static int occupied(const or_tctx* T, uint32_t ci, uint32_t k, const int64_t c[3],
-                    const int64_t base[3], uint8_t* mat, uint32_t* skip, int32_t* elev) {
+                    const int64_t base[3], uint8_t* mat, uint32_t* skip, int32_t* elev,
+                    uint32_t* siblings, uint32_t* probes) {
   const or_world* w = T->w;
   const size_t i = (size_t)ci * w->lod_count + k;
   const uint32_t x = (uint32_t)(c[0] - base[0]), y = (uint32_t)(c[1] - base[1]), z = (uint32_t)(c[2] - base[2]);
@@ -709,7 +718,7 @@ static int occupied(const or_tctx* T, uint32_t ci, uint32_t k, const int64_t c[3
   if (!d) { *skip = (T->mode & 1) ? w->chunk_log2 - k : 0; *elev = (int32_t)(w->chunk_log2 - k); return 0; }
   uint32_t dfs = 0, lev = 0;
   const or_marks* mk = T->marks ? &T->marks[i] : NULL;
-  if (dag_lookup(d, x, y, z, &dfs, &lev, mk)) { *mat = dag_material(d, dfs, mk); return 1; }
+  if (dag_lookup(d, x, y, z, &dfs, &lev, mk, siblings)) { *mat = dag_material(d, dfs, mk, probes); return 1; }
   *skip = (T->mode & 1) ? lev : 0;
   *elev = (int32_t)lev;
   return 0;
@@ -771,11 +780,15 @@ static void trace_one(const or_tctx* T, const int64_t O[3], const int64_t D[3], 
     for (int a = 0; a < 3; a++) c[a] = cell_at(O[a], D[a], cur, k);
     for (;;) {
       uint8_t mat = 0;
-      uint32_t skip = 0;
+      uint32_t skip = 0, siblings = 0, probes = 0;
       int32_t elev = -1;
-      const int solid = occupied(T, ci, (uint32_t)k, c, base, &mat, &skip, &elev);
+      const int solid = occupied(T, ci, (uint32_t)k, c, base, &mat, &skip, &elev, &siblings, &probes);
       if (counting) count_cubes(cnt, c, base, elev, CL - k, prev, &have_prev);
       if (solid) {
+        if (counting) {
+          cnt->preceding_siblings = (int32_t)siblings;
+          cnt->run_probes = (int32_t)probes;
+        }
         h->hit = 1;
         h->x = (int32_t)(c[0] << k); h->y = (int32_t)(c[1] << k); h->z = (int32_t)(c[2] << k);
         h->lod = k;

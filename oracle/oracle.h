@@ -104,9 +104,13 @@ void or_trace(const or_world* w, const uint8_t* lods, const int64_t O[3], const 
 /* Per-ray visit counts of the hierarchical traversal (DAG modes only):
  * chunks the ray passes through, non-empty chunk DAGs it enters, non-empty
  * internal-node cubes (levels 3 .. root-1) and leaf cubes (level 2) it
- * enters before its hit.  Used to state algorithmic memory traffic. */
+ * enters up to and including its hit; at a hit, the preceding set siblings
+ * summed over the internal levels of the hit cell's path (the subtree counts
+ * its DFS index adds up, Section 3.3) and the run starts the material search
+ * compares.  Used to state algorithmic memory traffic. */
 typedef struct {
   int32_t chunk_visits, chunk_entries, node_cubes, leaf_cubes;
+  int32_t preceding_siblings, run_probes;
 } or_counts;
 
 /* Trace the pixels idx[0..n) (idx = px + W*py; all pixels if idx is NULL)

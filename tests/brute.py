@@ -112,10 +112,88 @@ def brute_trace(chunk_log2, grid, lod_grids, lods, O, D):
                     face = 1 + 2 * a + (1 if D[a] < 0 else 0)
                     break
             best = (e[0], key[1], dict(hit=1, x=v[0], y=v[1], z=v[2], lod=k, material=m,
-                                       chunk=ci, face=face, t_rational=e[0]))
+                                       chunk=ci, face=face, t_rational=e[0], key=key))
     if best is None:
-        return dict(hit=0, x=0, y=0, z=0, lod=0, material=0, chunk=-1, face=0, t_rational=None)
+        return dict(hit=0, x=0, y=0, z=0, lod=0, material=0, chunk=-1, face=0, t_rational=None, key=None)
     return best[2]
+
+
+def _occupied_cubes(g: np.ndarray, level: int) -> np.ndarray:
+    """Per cube of 2^level cells: does it hold a solid cell ([z, y, x])."""
+    n = g.shape[0] >> level
+    e = 1 << level
+    return (g > 0).reshape(n, e, n, e, n, e).any(axis=(1, 3, 5))
+
+
+def brute_counts(chunk_log2, grid, lod_grids, lods, O, D):
+    """Visit counts by definition, from the grids alone (no stepping):
+
+    * chunk_visits: chunks whose box the ray enters at or before its hit
+      (all it enters, on a miss);
+    * chunk_entries: those of them whose grid at the picked LOD is not empty;
+    * node_cubes / leaf_cubes: non-empty cubes of 2^l cells (3 <= l < root,
+      resp. l = 2) of those grids that the ray enters at or before its hit;
+    * preceding_siblings: at a hit, over the internal levels l = root .. 3 of
+      the hit cell's path, the non-empty child cubes whose octant comes
+      before the path's (the counts the DFS index of Section 3.3 adds up).
+
+    An entry instant is compared with the hit's by (t, open-after-closed),
+    as the interval arithmetic gives them."""
+    hit = brute_trace(chunk_log2, grid, lod_grids, lods, O, D)
+    hk = hit["key"]
+    S = 1 << chunk_log2
+
+    def before(e):
+        return e is not None and (hk is None or (e[0], 1 if e[1] else 0) <= hk)
+
+    out = dict(chunk_visits=0, chunk_entries=0, node_cubes=0, leaf_cubes=0, preceding_siblings=0)
+    for cz in range(grid[2]):
+        for cy in range(grid[1]):
+            for cx in range(grid[0]):
+                ci = cx + grid[0] * (cy + grid[1] * cz)
+                base = (cx * S, cy * S, cz * S)
+                e = cell_entry(O, D, [b * FIX for b in base], [(b + S) * FIX for b in base])
+                if not before(e):
+                    continue
+                out["chunk_visits"] += 1
+                k = int(lods[ci])
+                g = lod_grids[ci][k]
+                if not g.any():
+                    continue
+                out["chunk_entries"] += 1
+                top = g.shape[0].bit_length() - 1
+                for l in range(2, top):
+                    edge = 1 << (l + k)  # voxels
+                    for z, y, x in zip(*np.nonzero(_occupied_cubes(g, l))):
+                        lo = (base[0] + int(x) * edge, base[1] + int(y) * edge, base[2] + int(z) * edge)
+                        e = cell_entry(O, D, [v * FIX for v in lo], [(v + edge) * FIX for v in lo])
+                        if before(e):
+                            out["node_cubes" if l >= 3 else "leaf_cubes"] += 1
+    if hit["hit"]:
+        ci, k = hit["chunk"], hit["lod"]
+        c = (ci % grid[0], (ci // grid[0]) % grid[1], ci // (grid[0] * grid[1]))
+        v = [(hit[ax] - c[a] * S) >> k for a, ax in enumerate("xyz")]
+        g = lod_grids[ci][k]
+        top = g.shape[0].bit_length() - 1
+        for l in range(top, 2, -1):
+            occ = _occupied_cubes(g, l - 1)
+            node = [(v[a] >> l) << 1 for a in range(3)]  # first child cube of the node, per axis
+            o = sum(((v[a] >> (l - 1)) & 1) << a for a in range(3))
+            for i in range(o):
+                if occ[node[2] + ((i >> 2) & 1), node[1] + ((i >> 1) & 1), node[0] + (i & 1)]:
+                    out["preceding_siblings"] += 1
+    return hit, out
+
+
+def run_count(g: np.ndarray) -> int:
+    """Maximal runs of equal material along the depth-first order of the
+    solid cells of g ([z, y, x])."""
+    R = g.shape[0]
+    zz, yy, xx = np.nonzero(g)
+    if zz.size == 0:
+        return 0
+    mats = g[zz, yy, xx][np.argsort(morton_rank(R, xx, yy, zz))]
+    return 1 + int(np.count_nonzero(mats[1:] != mats[:-1]))
 
 
 def euclid_t(t_rational: Fraction, D) -> float:
