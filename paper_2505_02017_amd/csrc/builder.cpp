@@ -66,6 +66,18 @@ void downsample(const uint8_t* src, uint32_t R, uint8_t* dst) {
       const uint8_t* d = c + r;          // y+1, z+1
       uint8_t* o = dst + h * (y + h * z);
       for (size_t x = 0; x < h; x++) {
+        if ((x & 3) == 0 && x + 4 <= h) {  // 4 coarse cells whose 32 voxels share one value
+          uint64_t qa, qb, qc, qd;
+          memcpy(&qa, a + 2 * x, 8);
+          memcpy(&qb, b + 2 * x, 8);
+          memcpy(&qc, c + 2 * x, 8);
+          memcpy(&qd, d + 2 * x, 8);
+          if (qa == qb && qa == qc && qa == qd && qa == 0x0101010101010101ull * (qa & 0xFF)) {
+            memset(o + x, (int)(qa & 0xFF), 4);
+            x += 3;
+            continue;
+          }
+        }
         uint16_t wa, wb, wc, wd;
         memcpy(&wa, a + 2 * x, 2);
         memcpy(&wb, b + 2 * x, 2);
@@ -196,19 +208,30 @@ struct RunBuilder {
   }
 };
 
-void dfs_runs(const LodData& L, const uint8_t* g, uint32_t off, int lev, uint32_t x0, uint32_t y0,
-              uint32_t z0, RunBuilder& rb) {
+// uni[l] (per cube of 2^l cells of the grid, x fastest, l >= 2): m when
+// every cell of the cube holds material m, else 0.  Such a cube adds at most
+// one run, whatever its size.
+void dfs_runs(const LodData& L, const uint8_t* g, const std::vector<std::vector<uint8_t>>& uni, uint32_t off,
+              int lev, uint32_t x0, uint32_t y0, uint32_t z0, RunBuilder& rb) {
   const LeafTables& T = leaf_tables();
   const size_t R = L.R;
   const uint32_t mask = L.words[off];
   const uint32_t h = 1u << (lev - 1);
+  const size_t nc = R >> (lev - 1);  // child cubes per axis
+  const std::vector<uint8_t>& cu = uni[lev - 1];
   uint32_t slot = 0;
   for (int o = 0; o < 8; o++) {
     if (!((mask >> o) & 1)) continue;
     const uint32_t p = L.words[off + 2 + slot++];
     const uint32_t cx = x0 + ((o & 1) ? h : 0), cy = y0 + ((o & 2) ? h : 0), cz = z0 + ((o & 4) ? h : 0);
+    const uint8_t m = cu[(cx >> (lev - 1)) + nc * ((cy >> (lev - 1)) + nc * (cz >> (lev - 1)))];
+    if (m) {
+      rb.push(m);
+      rb.i += (lev > 3 ? L.words[p + 1] : 64u) - 1;
+      continue;
+    }
     if (lev > 3) {
-      dfs_runs(L, g, p, lev - 1, cx, cy, cz, rb);
+      dfs_runs(L, g, uni, p, lev - 1, cx, cy, cz, rb);
       continue;
     }
     uint64_t bits = L.leaves[p];
@@ -242,22 +265,65 @@ int build_lod(const uint8_t* g, uint32_t R, LodData& L) {
   uint32_t base_bit[4][4];
   for (int z = 0; z < 4; z++)
     for (int y = 0; y < 4; y++) base_bit[y][z] = T.bit[4 * y + 16 * z];
+  std::vector<std::vector<uint8_t>> unis(Lr + 1);
+  unis[2].assign(n * n * n, 0);
+  std::vector<uint8_t>& uni = unis[2];
+  uint64_t last_bits = 0;
+  uint32_t last_id = 0;
   for (size_t bz = 0; bz < n; bz++)
     for (size_t by = 0; by < n; by++)
       for (size_t bx = 0; bx < n; bx++) {
+        if ((bx & 3) == 0 && bx + 4 <= n) {  // 4 blocks whose 256 voxels share one value
+          const uint8_t v = g[4 * bx + r * (4 * by + r * 4 * bz)];
+          const uint64_t v8 = 0x0101010101010101ull * v;
+          bool one = true;
+          for (int z = 0; z < 4 && one; z++)
+            for (int y = 0; y < 4 && one; y++) {
+              uint64_t q[2];
+              memcpy(q, g + 4 * bx + r * ((4 * by + y) + r * (4 * bz + z)), 16);
+              one = q[0] == v8 && q[1] == v8;
+            }
+          if (one) {
+            if (v) {
+              if (last_bits != ~0ull) {
+                last_bits = ~0ull;
+                last_id = lt.intern(~0ull);
+              }
+              for (size_t i = 0; i < 4; i++) {
+                cur[bx + i + n * (by + n * bz)] = last_id;
+                uni[bx + i + n * (by + n * bz)] = v;
+              }
+            }
+            bx += 3;
+            continue;
+          }
+        }
         uint64_t bits = 0;
+        const uint32_t m4 = 0x01010101u * g[4 * bx + r * (4 * by + r * 4 * bz)];
+        bool same = m4 != 0;
         for (int z = 0; z < 4; z++)
           for (int y = 0; y < 4; y++) {
             uint32_t row;
             memcpy(&row, g + 4 * bx + r * ((4 * by + y) + r * (4 * bz + z)), 4);
+            same = same && row == m4;
             if (!row) continue;
             const uint32_t b = base_bit[y][z];
+            if (!((row - 0x01010101u) & ~row & 0x80808080u)) {  // no zero byte: 4 solid voxels
+              bits |= 0x303ull << b;
+              continue;
+            }
             if (row & 0x000000FFu) bits |= 1ull << b;
             if (row & 0x0000FF00u) bits |= 1ull << (b + 1);
             if (row & 0x00FF0000u) bits |= 1ull << (b + 8);
             if (row & 0xFF000000u) bits |= 1ull << (b + 9);
           }
-        if (bits) cur[bx + n * (by + n * bz)] = lt.intern(bits);
+        if (!bits) continue;
+        if (same) uni[bx + n * (by + n * bz)] = (uint8_t)m4;
+        if (bits != last_bits) {  // neighbouring leaves are often equal (full, or one pattern)
+          last_bits = bits;
+          last_id = lt.intern(bits);
+        }
+        cur[bx + n * (by + n * bz)] = last_id;
       }
   // levels 3 .. root
   std::vector<NodeTable> tabs(Lr + 1);
@@ -265,20 +331,25 @@ int build_lod(const uint8_t* g, uint32_t R, LodData& L) {
     const size_t m = R >> lev, cn = 2 * m;
     std::vector<uint32_t> next(m * m * m, ~0u);
     NodeTable& tab = tabs[lev];
+    unis[lev].assign(m * m * m, 0);
+    const std::vector<uint8_t>& cu = unis[lev - 1];
     for (size_t z = 0; z < m; z++)
       for (size_t y = 0; y < m; y++)
         for (size_t x = 0; x < m; x++) {
           TNode t;
           t.mask = 0;
           t.count = 0;
+          uint8_t u = cu[2 * x + cn * (2 * y + cn * 2 * z)];
           for (int o = 0; o < 8; o++) {
             const size_t cx = 2 * x + (o & 1), cy = 2 * y + ((o >> 1) & 1), cz = 2 * z + ((o >> 2) & 1);
+            if (cu[cx + cn * (cy + cn * cz)] != u) u = 0;
             const uint32_t id = cur[cx + cn * (cy + cn * cz)];
             t.child[o] = id;
             if (id == ~0u) continue;
             t.mask |= 1u << o;
             t.count += (lev == 3) ? (uint32_t)__builtin_popcountll(lt.vals[id]) : tabs[lev - 1].nodes[id].count;
           }
+          unis[lev][x + m * (y + m * z)] = u;
           if (t.mask) next[x + m * (y + m * z)] = tab.intern(t);
         }
     cur.swap(next);
@@ -343,7 +414,7 @@ int build_lod(const uint8_t* g, uint32_t R, LodData& L) {
   for (size_t i = 0; i < leaf_order.size(); i++) L.leaves[i] = lt.vals[leaf_order[i]];
   L.n_solid = L.words[1];
   RunBuilder rb{&L.rle_start, &L.rle_mat};
-  dfs_runs(L, g, 0, Lr, 0, 0, 0, rb);
+  dfs_runs(L, g, unis, 0, Lr, 0, 0, 0, rb);
   if (rb.i != L.n_solid) return svd_fail(SVD_EINVAL, "internal: DFS count mismatch");
   if (!node_boxes(L, nullptr, L.lo, L.hi)) return svd_fail(SVD_EINVAL, "internal: bad DAG");
   return SVD_OK;
