@@ -70,6 +70,26 @@ def test_builder_matches_oracle_generated():
     _compare_blob(svdag, sw.chunk((1, 0, 0)), 128, 4)
 
 
+def test_builder_matches_oracle_uniform_regions():
+    """Large regions of one material (the builder's uniform fast paths),
+    with single voxels and rows that break them at every alignment: a
+    different material, an empty voxel, a run that starts mid-block."""
+    svdag = _svdag()
+    rng = np.random.default_rng(12)
+    R = 64
+    z = np.arange(R)[:, None, None]
+    g = np.broadcast_to(np.where(z < 40, 1 + z // 8, 0), (R, R, R)).astype(np.uint8).copy()
+    g[20:28, 8:40, 16:48] = 0                                   # a cave
+    g[8:12, 4:8, 0:64] = 9                                      # a row of another material
+    for _ in range(60):                                         # isolated breaks
+        x, y, zz = (int(v) for v in rng.integers(0, R, 3))
+        g[zz, y, x] = int(rng.integers(0, 16))
+    _compare_blob(svdag, g.reshape(-1), R, 4)
+    g2 = np.full((R, R, R), 7, np.uint8)
+    g2[:, :, 1::4] = 5                                          # breaks every 4-voxel row
+    _compare_blob(svdag, g2.reshape(-1), R, 3)
+
+
 def test_builder_empty_and_full():
     svdag = _svdag()
     b = _compare_blob(svdag, np.zeros(32 ** 3, np.uint8), 32, 3)
