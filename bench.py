@@ -79,26 +79,143 @@ def counter_profile(workload):
     return vals
 
 
-def bytes_per_ray(counts, hits, lods, chunk_log2, n_rle, sector=0):
-    """Algorithmic bytes of the trace kernel for each ray (the canonical visit
-    set that the oracle's counting mode replays):
-    4 B view entry per chunk visited; 20 B per chunk DAG entered (node and
-    leaf array addresses, root word); 4 B child word per internal node
-    entered; 12 B (child word + bitmap) per leaf entered; at a hit 28 B
-    (prefix and run array addresses, run count), 4 B per internal level
-    (DFS prefix), 4 B per run search step and 1 B material; the 16 B record.
-    With `sector` > 0, every one of those reads costs a whole sector of that
-    many bytes instead (the no-reuse upper bound; the record stays 16 B)."""
+def bytes_per_ray(counts, hits):
+    """Algorithmic bytes per ray of the hierarchical traversal, in the
+    paper's node format (Section 3.2) and material scheme (Section 3.3), from
+    the oracle's visit counts: 8 B (header word and child pointer) per
+    internal node descended, the chunk's root included; 8 B per 4^3 leaf
+    bitmap; at a hit, 4 B per preceding-sibling subtree count that the DFS
+    index adds up, 4 B per run start the block search compares and 1 B of
+    material; and the 16 B record."""
+    b = (8.0 * (counts["chunk_entries"] + counts["node_cubes"]) + 8.0 * counts["leaf_cubes"] + 16.0)
+    h = hits["hit"] == 1
+    b[h] += 4.0 * counts["preceding_siblings"][h] + 4.0 * counts["run_probes"][h] + 1.0
+    return b
+
+
+def layout_bytes_per_ray(counts, hits, chunk_log2, sector=0):
+    """Bytes per ray that this library's device layout reads for the same
+    visits: 4 B view entry per chunk visited; 20 B per chunk DAG entered
+    (node and leaf array addresses, root word); 4 B child word per internal
+    node entered (the child's mask rides in its parent's word); 12 B (child
+    word + bitmap) per leaf entered; at a hit 28 B (prefix and run array
+    addresses, run count), one 4-B DFS prefix per internal level (the
+    siblings' counts are summed ahead of time), 4 B per run start compared
+    and 1 B material; the 16 B record.  With `sector` > 0 every one of those
+    reads costs a whole sector of that many bytes instead (the no-reuse
+    upper bound; the record stays 16 B)."""
     def rd(nbytes, accesses):
         return sector * accesses if sector else nbytes
     b = (rd(4.0, 1) * counts["chunk_visits"] + rd(20.0, 1) * counts["chunk_entries"] +
          rd(4.0, 1) * counts["node_cubes"] + rd(12.0, 2) * counts["leaf_cubes"] + 16.0)
     h = hits["hit"] == 1
     k = hits["lod"][h]
-    nr = n_rle[hits["chunk"][h], k]
-    steps = np.ceil(np.log2(np.maximum(nr, 1)))
-    b[h] += rd(28.0, 1) + rd(4.0, 1) * (chunk_log2 - k - 2) + rd(4.0, 1) * steps + rd(1.0, 1)
+    b[h] += (rd(28.0, 1) + rd(4.0, 1) * (chunk_log2 - k - 2) + rd(4.0, 1) * counts["run_probes"][h] +
+             rd(1.0, 1))
     return b
+
+
+def host_cores():
+    """(cores, nproc, cgroup limit): the CPUs this process may run on (what
+    nproc reports), cut to the cgroup's CPU quota when one is set (threads
+    beyond it would only time-slice)."""
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    limit = None
+    try:
+        q, per = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            limit = int(q) / int(per)
+    except (OSError, ValueError):
+        pass
+    cores = nproc if limit is None else max(1, min(nproc, int(limit)))
+    return cores, nproc, limit
+
+
+def build_chunks(args, sw, lod_count, gen, svdag, torch, ow=None, need=None):
+    """Every chunk of the scene generated once (on the host, or on the GPU and
+    copied into pinned host buffers) and built into a library blob (all
+    LODs) by a pool of host threads; with an oracle world `ow`, the oracle's
+    own DAGs of the LODs need[ci] are built from the same bytes and set in
+    it (test infrastructure, for the CPU-baseline leg only)."""
+    CL = sw.chunk_log2
+    gx, gy, gz = sw.grid
+    nch = gx * gy * gz
+    t0 = time.time()
+    blobs = {}
+    if ow is not None:
+        import oracle
+
+    def work(ci, g=None):
+        c = (ci % gx, (ci // gx) % gy, ci // (gx * gy))
+        if g is None:
+            g = sw.chunk(c, threads=1 if nch > 1 else args.threads)
+        b = svdag.svd_chunk_build(g, CL, lod_count)
+        odags = []
+        if ow is not None and need[ci]:
+            pyr = oracle.pyramid(g, 1 << CL, max(need[ci]) + 1)
+            for k in sorted(need[ci]):
+                odags.append((k, oracle.Dag(pyr[k], (1 << CL) >> k)))
+        return ci, b, odags
+
+    def gpu_generated(ex):
+        """Chunks generated on the GPU one at a time (one S^3 device buffer),
+        copied to a pinned host buffer and built by the pool; host buffers
+        are recycled as builds finish."""
+        import collections
+        import queue
+        S = 1 << CL
+        dev = torch.empty(S ** 3, dtype=torch.uint8, device="cuda")
+        free = queue.Queue()
+        for _ in range(args.threads + 2):
+            free.put(torch.empty(S ** 3, dtype=torch.uint8, pin_memory=True))
+        work_dev = None
+
+        def build_and_recycle(ci, h):
+            try:
+                return work(ci, h.numpy())
+            finally:
+                free.put(h)
+
+        futs = collections.deque()
+        for ci in range(nch):
+            h = free.get()
+            work_dev = sw.chunk_device((ci % gx, (ci // gx) % gy, ci // (gx * gy)), dev, work_dev)
+            h.copy_(dev)  # synchronous: the buffer is complete when the build starts
+            futs.append(ex.submit(build_and_recycle, ci, h))
+            while futs and futs[0].done():
+                yield futs.popleft().result()
+        while futs:
+            yield futs.popleft().result()
+
+    with ThreadPoolExecutor(args.threads) as ex:
+        results = gpu_generated(ex) if gen == "gpu" else ex.map(work, range(nch))
+        for n_done, (ci, b, odags) in enumerate(results, 1):
+            blobs[ci] = b
+            for k, d in odags:
+                ow.set_dag(ci, k, d)
+            if n_done % 64 == 0:
+                log(f"  {n_done}/{nch} chunks built ({time.time() - t0:.1f}s)")
+    log(f"built {nch} chunks ({lod_count} LODs) in {time.time() - t0:.1f}s")
+    return blobs
+
+
+def make_world(sw, blobs, lod_count, thr, svdag, torch):
+    """A world over a pool that holds every chunk LOD, all uploaded."""
+    gx, gy, gz = sw.grid
+    nch = gx * gy * gz
+    desc = svdag.make_desc(sw.chunk_log2, sw.grid, lod_count, thr)
+    dev_bytes = sum(svdag.svd_blob_stats_get(b, k)["device_bytes"] for b in blobs.values()
+                    for k in range(lod_count))
+    pool = torch.empty(svdag.table_bytes(sw.grid) + dev_bytes + 256 * nch * lod_count + (8 << 20),
+                       dtype=torch.uint8, device="cuda")
+    world = svdag.svd_world_create(desc, pool)
+    for ci, b in blobs.items():
+        svdag.svd_chunk_upload(world, (ci % gx, (ci // gx) % gy, ci // (gx * gy)), b)
+    torch.cuda.synchronize()
+    return world, pool, dev_bytes
 
 
 def main():
@@ -113,13 +230,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle legs (CPU baseline and visit counts)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-baseline time")
-    ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1),
+                    help="host threads that build the chunks")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the CPU baseline (0 = every core this process may use)")
     ap.add_argument("--batch-views", type=int, default=64,
                     help="views in the batched-launch comparison (0 = skip it)")
     ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="length of each fixed-rate serving run (0 = skip the served comparison)")
-    ap.add_argument("--serve-rates", default="200,2000", help="request arrival rates (req/s)")
+    ap.add_argument("--serve-rates", default="2000", help="request arrival rates on the workload's map (req/s)")
     ap.add_argument("--serve-backlog", type=int, default=1000,
                     help="requests of the saturated run (as many in flight as output buffers)")
     ap.add_argument("--serve-pool-frac", type=float, default=0.25,
@@ -134,9 +254,16 @@ def main():
     ap.add_argument("--gen", choices=("host", "gpu"), default="host",
                     help="generate the scene's chunks on the host or with the GPU copy of the generator "
                          "(same bytes; gpu makes map1024 practical)")
+    ap.add_argument("--c4-seconds", type=float, default=32.0,
+                    help="length of each served run on map1024 (0 = skip that leg)")
+    ap.add_argument("--c4-rate", type=float, default=200.0, help="request arrival rate on map1024 (req/s)")
+    ap.add_argument("--time-budget", type=float, default=540.0,
+                    help="seconds the whole run may take: the map1024 leg is skipped (and said so) "
+                         "if it would not fit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
+    t_begin = time.time()
     if args.copy_calibration:
         import torch
         n = args.copy_calibration << 20
@@ -173,84 +300,19 @@ def main():
 
     # ---- oracle side: which (chunk, LOD) DAGs the sampled views need
     ow = None
-    n_rle = np.ones((nch, 4), np.int64)
-    need = [set() for _ in range(nch)]
+    need = None
     if use_oracle:
         import oracle
         ow = oracle.World(CL, sw.grid, lod_count)
         frames = [oracle.camera_frame(c) for c in cams]
         view_lods = [ow.lod_pick(f.O, thr) for f in frames]
+        need = [set() for _ in range(nch)]
         for vl in view_lods:
             for ci in range(nch):
                 need[ci].add(int(vl[ci]))
 
-    # ---- generate every chunk once; build the library blob (all LODs) and
-    #      the oracle's DAGs for the LODs the sampled views use
-    t0 = time.time()
-    blobs = {}
-
-    def work(ci, g=None):
-        c = (ci % gx, (ci // gx) % gy, ci // (gx * gy))
-        if g is None:
-            g = sw.chunk(c, threads=1 if nch > 1 else args.threads)
-        b = svdag.svd_chunk_build(g, CL, lod_count)
-        odags = []
-        if ow is not None and need[ci]:
-            pyr = oracle.pyramid(g, 1 << CL, max(need[ci]) + 1)
-            for k in sorted(need[ci]):
-                odags.append((k, oracle.Dag(pyr[k], (1 << CL) >> k)))
-        return ci, b, odags
-
-    def gpu_generated(ex):
-        """Chunks generated on the GPU one at a time (one S^3 device buffer),
-        copied to a host buffer and built by the pool; host buffers are
-        recycled as builds finish."""
-        import queue
-        S = 1 << CL
-        dev = torch.empty(S ** 3, dtype=torch.uint8, device="cuda")
-        free = queue.Queue()
-        for _ in range(args.threads + 2):
-            free.put(np.empty(S ** 3, np.uint8))
-        work_dev = None
-
-        def build_and_recycle(ci, g):
-            try:
-                return work(ci, g)
-            finally:
-                free.put(g)
-
-        import collections
-        futs = collections.deque()
-        for ci in range(nch):
-            g = free.get()
-            work_dev = sw.chunk_device((ci % gx, (ci // gx) % gy, ci // (gx * gy)), dev, work_dev)
-            torch.from_numpy(g).copy_(dev)  # synchronous on this stream
-            futs.append(ex.submit(build_and_recycle, ci, g))
-            while futs and futs[0].done():
-                yield futs.popleft().result()
-        while futs:
-            yield futs.popleft().result()
-
-    with ThreadPoolExecutor(args.threads) as ex:
-        results = gpu_generated(ex) if args.gen == "gpu" else ex.map(work, range(nch))
-        for ci, b, odags in results:
-            blobs[ci] = b
-            for k, d in odags:
-                n_rle[ci, k] = d.d.n_rle
-                ow.set_dag(ci, k, d)
-            if (ci + 1) % 32 == 0:
-                log(f"  {ci + 1}/{nch} chunks built ({time.time() - t0:.1f}s)")
-    log(f"built {nch} chunks ({lod_count} LODs) in {time.time() - t0:.1f}s")
-
-    desc = svdag.make_desc(CL, sw.grid, lod_count, thr)
-    dev_bytes = sum(svdag.svd_blob_stats_get(b, k)["device_bytes"] for b in blobs.values()
-                    for k in range(lod_count))
-    pool = torch.empty(svdag.table_bytes(sw.grid) + dev_bytes + 256 * nch + (8 << 20),
-                       dtype=torch.uint8, device="cuda")
-    world = svdag.svd_world_create(desc, pool)
-    for ci, b in blobs.items():
-        svdag.svd_chunk_upload(world, (ci % gx, (ci // gx) % gy, ci // (gx * gy)), b)
-    torch.cuda.synchronize()
+    blobs = build_chunks(args, sw, lod_count, args.gen, svdag, torch, ow, need)
+    world, pool, dev_bytes = make_world(sw, blobs, lod_count, thr, svdag, torch)
     log(f"uploaded {dev_bytes / 2**20:.1f} MiB of chunk DAGs")
 
     frames_gpu = [svdag.svd_camera_frame(c) for c in cams]
@@ -339,32 +401,38 @@ def main():
     }
 
     if use_oracle:
+        cores, nproc, cg_limit = host_cores()
+        cpu_threads = args.cpu_threads or cores
         # ---- algorithmic bytes per ray: oracle visit counts on a sparse sample of every view
         stride = 97
-        per_ray, per_ray_sec = [], []
+        per_ray, per_ray_layout, per_ray_sec = [], [], []
         for v, f in enumerate(frames):
             idx = np.arange(v % stride, W * H, stride, dtype=np.uint32)
-            h, cnt = ow.trace_frame(view_lods[v], f, idx, mode=1, threads=args.threads, counts=True)
-            per_ray.append(bytes_per_ray(cnt, h, view_lods[v], CL, n_rle))
-            per_ray_sec.append(bytes_per_ray(cnt, h, view_lods[v], CL, n_rle, sector=64))
-        mean_b = float(np.concatenate(per_ray).mean())
-        mean_b_sec = float(np.concatenate(per_ray_sec).mean())
+            h, cnt = ow.trace_frame(view_lods[v], f, idx, mode=1, threads=cpu_threads, counts=True)
+            per_ray.append(bytes_per_ray(cnt, h))
+            per_ray_layout.append(layout_bytes_per_ray(cnt, h, CL))
+            per_ray_sec.append(layout_bytes_per_ray(cnt, h, CL, sector=64))
         # per-view launches cycle over the views; weight each view's bytes by its launches
         nviews = len(frames)
-        view_b = np.array([p.mean() for p in per_ray])
         launches = np.bincount(np.arange(args.steps) % nviews, minlength=nviews)
-        bytes_per_launch = float((view_b * launches).sum() / launches.sum()) * W * H
+
+        def per_launch(rays_bytes):
+            view_b = np.array([p.mean() for p in rays_bytes])
+            return float((view_b * launches).sum() / launches.sum()) * W * H
+        bytes_per_launch = per_launch(per_ray)
+        layout_per_launch = per_launch(per_ray_layout)
         # compulsory bytes: every part of the device layout a view's rays
         # touch, counted once (child words, leaf bitmaps, prefix counts, run
         # starts and materials, view-table entries, 64-B descriptors), plus
         # the records
         comp = []
         for v, f in enumerate(frames):
-            t = ow.touch_frame(view_lods[v], f, threads=args.threads)
+            t = ow.touch_frame(view_lods[v], f, threads=cpu_threads)
             comp.append(4 * t["child_words"] + 8 * t["leaves"] + 4 * t["prefixes"] + 4 * t["run_starts"] +
                         t["run_materials"] + 4 * t["chunks"] + 64 * t["dags"] + 16 * t["rays"])
         compulsory = float((np.array(comp, np.float64) * launches).sum() / launches.sum())
-        achieved = bytes_per_launch / (pass_ms.mean() * 1e-3) / 1e9
+        launch_s = pass_ms.mean() * 1e-3
+        achieved = bytes_per_launch / launch_s / 1e9
         prof = counter_profile(args.workload)
         traffic = float(prof["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in prof else None
         result["roofline"] = {
@@ -372,34 +440,48 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 5),
             "traffic": round(traffic) if traffic is not None else None,
             "kernel": "beam_kernel + trace_kernel" if args.beam else "trace_kernel",
-            "bytes_per_ray": round(mean_b, 2),
-            "bytes_per_launch": round(bytes_per_launch), "launch_ms": round(float(pass_ms.mean()), 4),
-            # no-reuse upper bound: every read a whole 64-B sector
-            "sector64_bytes_per_ray": round(mean_b_sec, 2),
+            "launch_ms": round(float(pass_ms.mean()), 4),
+            # frac: the paper's node format and DFS resolve (preceding-sibling
+            # counts), from the oracle's pinned visit counts
+            "bytes_per_ray": round(float(np.concatenate(per_ray).mean()), 2),
+            "bytes_per_launch": round(bytes_per_launch),
+            # the same visits in this library's device layout
+            "layout_bytes_per_ray": round(float(np.concatenate(per_ray_layout).mean()), 2),
+            "layout_frac": round(layout_per_launch / launch_s / 1e9 / HBM_PEAK_GBS, 5),
+            # no-reuse upper bound: every layout read a whole 64-B sector
+            "sector64_bytes_per_ray": round(float(np.concatenate(per_ray_sec).mean()), 2),
             # compulsory lower bound: each touched byte once (records included)
             "compulsory_bytes_per_launch": round(compulsory),
             "record_bytes_per_launch": W * H * 16,
+            # what HBM actually moved (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)
+            "hbm_measured_gbs": round(traffic / launch_s / 1e9, 2) if traffic is not None else None,
+            "hbm_measured_frac": round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 5) if traffic is not None else None,
             "blocks_per_cu": int(svdag.svd_world_get_occupancy(world)[0]),
         }
         if "l1_hit_rate" in prof:
             result["caches"] = {"l1_hit_rate": float(prof["l1_hit_rate"]), "l2_hit_rate": float(prof["l2_hit_rate"]),
                                 "source": "rocprofv3 TCP/TCC counters in profiles/ (same kernel source)"}
+            if "mall_hit_rate" in prof:
+                result["caches"]["mall_hit_rate"] = float(prof["mall_hit_rate"])
         if "valu_insts_per_launch" in prof:
             # VALU issue view: wave instructions per second over the issue peak
             # (1024 SIMDs x 2.4 GHz / 4 cycles per wave64 VALU instruction)
             rate = float(prof["valu_insts_per_launch"]) / (trace_ms.mean() * 1e-3)  # trace kernel alone
             peak = 1024 * 2.4e9 / 4
             result["valu_issue"] = {"achieved": round(rate / 1e9, 2), "peak": round(peak / 1e9, 2),
-                                    "unit": "G wave-instructions/s", "frac": round(rate / peak, 4)}
+                                    "unit": "G wave-instructions/s", "frac": round(rate / peak, 4),
+                                    "insts_per_launch": int(float(prof["valu_insts_per_launch"]))}
             if "valu_lane_utilisation" in prof:
                 result["valu_issue"]["lane_utilisation"] = float(prof["valu_lane_utilisation"])
+            # the unit that binds: VALU issue, not HBM
+            result["roofline"]["limiter"] = {"unit": "valu_issue", "frac": round(rate / peak, 4)}
         # ---- CPU baseline: the oracle (as is) on a bounded sample: whole views
         #      in benchmark order while the time budget lasts (repeated passes
         #      over all of them if they fit more than once, at most 8), else
         #      evenly spaced pixels of view 0
         pilot = np.arange(0, W * H, max(1, (W * H) // 4000), dtype=np.uint32)
         t = time.perf_counter()
-        ow.trace_frame(view_lods[0], frames[0], pilot, mode=1, threads=args.threads)
+        ow.trace_frame(view_lods[0], frames[0], pilot, mode=1, threads=cpu_threads)
         per = (time.perf_counter() - t) / pilot.size
         n_budget = int(max(1000, args.cpu_seconds / max(per, 1e-12)))
         nviews_cpu = max(1, min(nviews, n_budget // (W * H)))
@@ -409,7 +491,7 @@ def main():
         passes = 0
         while True:
             refs = [ow.trace_frame(view_lods[v], frames[v], sample0 if v == 0 else None, mode=1,
-                                   threads=args.threads) for v in range(nviews_cpu)]
+                                   threads=cpu_threads) for v in range(nviews_cpu)]
             passes += 1
             dt = time.perf_counter() - t
             # another pass over all views only if it still fits the budget
@@ -429,16 +511,48 @@ def main():
         if passes > 1:
             what += f", {passes} passes"
         result["cpu_baseline"] = {
-            "value": round(n / dt / 1e9, 6), "unit": "Grays/s", "cores": args.threads,
+            "value": round(n / dt / 1e9, 6), "unit": "Grays/s", "cores": cpu_threads,
             "kind": "oracle",
             "sample": f"{n} rays: {what} ({W}x{H}), oracle mode 1 (empty-subtree skipping), "
-                      f"{args.threads} threads, {dt:.1f}s",
+                      f"{cpu_threads} threads, {dt:.1f}s",
+            "nproc": nproc, "cgroup_cpu_limit": cg_limit,
         }
 
     if args.batch_views > 0:
         result["batched"] = bench_batched(args, sw, world, svdag, torch)
+    modes = ("batched", "plain", "plain_concurrent")
     if args.serve_seconds > 0:
-        result["served"] = bench_served(args, sw, blobs, lod_count, thr, world, svdag, torch)
+        # the workload's own map: rates where the walkers outgrow the pool
+        rates = [float(r) for r in args.serve_rates.split(",") if r]
+        result["served"] = bench_served(args, sw, blobs, lod_count, thr, world, svdag, torch, rates,
+                                        args.serve_seconds, modes, args.serve_backlog,
+                                        args.serve_streaming_factor)
+    del world, pool, out
+    blobs.clear()
+    ow = None
+    torch.cuda.empty_cache()
+    if args.c4_seconds > 0 and args.workload != "map1024":
+        # the served configuration: 32x32 chunks of 1024^3, pool at a quarter
+        # of the map, Poisson arrivals at 200 requests/s from walkers
+        elapsed = time.time() - t_begin
+        need_s = 150 + 4 * args.c4_seconds
+        if elapsed + need_s > args.time_budget:
+            result["served_map1024"] = {"skipped": f"time budget: {elapsed:.0f} s spent, about {need_s:.0f} s "
+                                                   f"more needed, {args.time_budget:.0f} s allowed"}
+        else:
+            kind4, lods4, thr4, desc4 = WORKLOADS["map1024"]
+            sw4 = scenes.SceneWorld(kind4, args.seed)
+            blobs4 = build_chunks(args, sw4, lods4, "gpu", svdag, torch)
+            world4, pool4, bytes4 = make_world(sw4, blobs4, lods4, thr4, svdag, torch)
+            log(f"map1024: uploaded {bytes4 / 2**30:.2f} GiB of chunk DAGs")
+            r = bench_served(args, sw4, blobs4, lods4, thr4, world4, svdag, torch, [args.c4_rate],
+                             args.c4_seconds, modes, args.serve_backlog, args.serve_streaming_factor)
+            r["workload"] = desc4.split(", 2560x1440")[0] + ", chunks generated on the GPU"
+            result["served_map1024"] = r
+            del world4, pool4
+            blobs4.clear()
+            torch.cuda.empty_cache()
+    result["bench_seconds"] = round(time.time() - t_begin, 1)
 
     print(json.dumps(result), flush=True)
 
@@ -504,12 +618,14 @@ def bench_batched(args, sw, world, svdag, torch):
     }
 
 
-def bench_served(args, sw, blobs, lod_count, thr, full_world, svdag, torch):
+def bench_served(args, sw, blobs, lod_count, thr, full_world, svdag, torch, rates, seconds, modes, backlog,
+                 prefetch_sf):
     """Served requests over a pool that holds a fraction of the map's chunk
     LODs: walkers issue Poisson-arriving views of mixed resolution; batched
-    continuous serving against per-request plain launches on the same
-    schedule, at fixed rates and saturated (as many requests in flight as
-    there are output buffers).  Latency = completion seen by the server's
+    continuous serving against per-request plain launches (serial on one
+    stream, and concurrent on the flights' own streams and tables) on the
+    same schedule, at fixed rates and saturated (as many requests in flight
+    as there are output buffers).  Latency = completion seen by the server's
     worker minus the request's scheduled arrival."""
     import threading
     gx, gy, gz = sw.grid
@@ -523,7 +639,6 @@ def bench_served(args, sw, blobs, lod_count, thr, full_world, svdag, torch):
     outs = torch.empty((ring, maxpx, 4), dtype=torch.int32, device="cuda")
     desc = svdag.make_desc(CL, sw.grid, lod_count, thr)
     views, inflight = args.serve_views, args.serve_inflight
-    rates = [float(r) for r in args.serve_rates.split(",") if r]
     old_switch = sys.getswitchinterval()
     sys.setswitchinterval(0.0005)
 
@@ -582,6 +697,7 @@ def bench_served(args, sw, blobs, lod_count, thr, full_world, svdag, torch):
         r = {"requests": n, "failed": failed, "grays": round(rays / span / 1e9, 4),
              "p50_ms": round(float(np.percentile(lat[warm], 50)), 3),
              "p99_ms": round(float(np.percentile(lat[warm], 99)), 3),
+             "measured_requests": int(warm.sum()),
              "mean_requests_per_launch": round(float(bv.mean()), 2), "launches": st["launches"],
              "uploads": st["uploads"], "upload_mib": round(st["upload_bytes"] / 2**20, 1),
              "evictions": st["evictions"], "memory_waits": st["memory_waits"],
@@ -599,26 +715,29 @@ def bench_served(args, sw, blobs, lod_count, thr, full_world, svdag, torch):
 
     res = {"pool_bytes_for_chunks": budget, "map_bytes_all_lods": all_bytes,
            "pool_fraction": args.serve_pool_frac, "walkers": 8, "walker_speed": args.serve_speed,
+           "seconds_per_run": seconds,
            "resolutions": "uniform over 320x180, 640x360, 1280x720, 1920x1080",
            "batched_launch": {"max_requests": views, "max_rays": args.serve_max_rays, "inflight": inflight},
-           "prefetch_streaming_factor": args.serve_streaming_factor,
+           "plain": "one stage + trace pair per request, serial on one stream",
+           "plain_concurrent": f"one stage + trace pair per request, up to {inflight} at once on their own "
+                               "streams and view tables",
+           "prefetch_streaming_factor": prefetch_sf,
            "latency": "scheduled arrival to completion; requests arriving in the first second "
                       "(cold pool) are served but not in the percentiles"}
-    modes = (("batched", svdag.SVD_SERVE_BATCHED), ("plain", svdag.SVD_SERVE_PLAIN))
+    mode_ids = {"batched": svdag.SVD_SERVE_BATCHED, "plain": svdag.SVD_SERVE_PLAIN,
+                "plain_concurrent": svdag.SVD_SERVE_PLAIN_CONCURRENT}
     for rate in rates:
-        sched = sw.walk_requests(8, rate, args.serve_seconds, seed=int(rate), speed=args.serve_speed)
-        for name, mode in modes:
+        sched = sw.walk_requests(8, rate, seconds, seed=int(rate), speed=args.serve_speed)
+        for name in modes:
             log(f"serving {len(sched)} requests at {rate:g}/s, {name}")
-            res[f"{name}_{rate:g}rps"] = run(mode, sched, False)
-        if args.serve_streaming_factor > 0:
+            res[f"{name}_{rate:g}rps"] = run(mode_ids[name], sched, False)
+        if prefetch_sf > 0:
             log(f"serving {len(sched)} requests at {rate:g}/s, batched with prefetch")
-            res[f"batched_prefetch_{rate:g}rps"] = run(svdag.SVD_SERVE_BATCHED, sched, False,
-                                                       args.serve_streaming_factor)
-    sched = sw.walk_requests(8, 400.0, args.serve_backlog / 400.0 + 1.0, seed=99,
-                             speed=args.serve_speed)[:args.serve_backlog]
-    for name, mode in (modes if args.serve_backlog > 0 else ()):
+            res[f"batched_prefetch_{rate:g}rps"] = run(svdag.SVD_SERVE_BATCHED, sched, False, prefetch_sf)
+    sched = sw.walk_requests(8, 400.0, backlog / 400.0 + 1.0, seed=99, speed=args.serve_speed)[:backlog]
+    for name in (modes if backlog > 0 else ()):
         log(f"serving {len(sched)} requests saturated, {name}")
-        res[f"{name}_saturated"] = run(mode, sched, True)
+        res[f"{name}_saturated"] = run(mode_ids[name], sched, True)
     sys.setswitchinterval(old_switch)
     del outs
     return res

@@ -353,7 +353,12 @@ int svd_batch_tune(svd_batch* b, const svd_camera* cams, uint32_t n, svd_hit* ou
  *     upload first);
  *   - SVD_SERVE_PLAIN traces each request with its own stage + trace launch
  *     pair, all on one stream, up to `inflight` queued (the per-request
- *     comparison);
+ *     comparison, serial);
+ *   - SVD_SERVE_PLAIN_CONCURRENT traces each request with its own stage +
+ *     trace launch pair too, but up to `inflight` of them run at once, each
+ *     on its own stream with its own view table and queue block (the
+ *     per-request comparison, concurrent; takes inflight x
+ *     svd_batch_create(w, 1) pool space);
  *   - with streaming_factor f > 0, the streaming policy of Section 3.4 runs
  *     whenever a request's camera enters a chunk not among the last 8 seen:
  *     an implicit octree over the chunk grid is walked from the root, a node
@@ -373,9 +378,10 @@ typedef struct svd_server svd_server;
 
 #define SVD_SERVE_BATCHED 0u
 #define SVD_SERVE_PLAIN 1u
+#define SVD_SERVE_PLAIN_CONCURRENT 2u
 
 typedef struct {
-  uint32_t mode;           /* SVD_SERVE_BATCHED or SVD_SERVE_PLAIN */
+  uint32_t mode;           /* SVD_SERVE_BATCHED, SVD_SERVE_PLAIN or SVD_SERVE_PLAIN_CONCURRENT */
   uint32_t max_views;      /* batched: requests per launch, 1..1024 */
   uint32_t inflight;       /* launches on the device at once, 1..8 */
   uint32_t tile_w, claim;  /* batched: tiling (0 = the batch default) */

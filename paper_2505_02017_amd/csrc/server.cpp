@@ -10,11 +10,12 @@
 //     that does not fit while other work holds memory waits; one that does
 //     not fit an idle pool fails with SVD_ENOMEM;
 //   - packs admitted requests into launches (batched mode: up to max_views
-//     requests and max_rays rays per captured batch graph; plain mode: one
-//     stage + trace launch pair per request) and keeps up to `inflight`
-//     launches on the device, so requests that arrive while others run are
-//     admitted as soon as a launch slot and memory free up (continuous
-//     batching);
+//     requests and max_rays rays per captured batch graph; plain modes: one
+//     stage + trace launch pair per request, serial on one stream or
+//     concurrent on the flights' own streams and view tables) and keeps up to
+//     `inflight` launches on the device, so requests that arrive while others
+//     run are admitted as soon as a launch slot and memory free up
+//     (continuous batching);
 //   - reaps finished launches (event query), unpins their slots and reports
 //     each request's submit, launch and completion times;
 //   - optionally runs the streaming policy of Section 3.4 (an implicit chunk
@@ -80,7 +81,7 @@ struct svd_server {
   hipEvent_t up_done = nullptr;      // recorded on `up` before a launch that follows new uploads
   bool up_dirty = false;             // uploads enqueued since up_done was last recorded
   bool up_pending = false;           // up_done has been recorded
-  hipStream_t plain = nullptr;       // plain mode: every launch (the world has one view table)
+  hipStream_t plain = nullptr;       // serial plain mode: every launch (on the world's view table)
   std::vector<Flight> fl;
   // streaming policy
   std::deque<std::array<int64_t, 4>> recent;  // last camera positions (2^16 units) and their chunk
@@ -515,7 +516,8 @@ static void server_release(svd_server* s) {
 extern "C" int svd_server_create(svd_world* w, const svd_server_desc* d, svd_server** out) {
   if (!w || !d || !out) return svd_fail(SVD_EINVAL, "svd_server_create: null argument");
   *out = nullptr;
-  if (d->mode != SVD_SERVE_BATCHED && d->mode != SVD_SERVE_PLAIN) return svd_fail(SVD_EINVAL, "serve: unknown mode");
+  if (d->mode != SVD_SERVE_BATCHED && d->mode != SVD_SERVE_PLAIN && d->mode != SVD_SERVE_PLAIN_CONCURRENT)
+    return svd_fail(SVD_EINVAL, "serve: unknown mode");
   if (d->inflight < 1 || d->inflight > 8) return svd_fail(SVD_EINVAL, "serve: inflight must be 1..8");
   if (d->mode == SVD_SERVE_BATCHED && (d->max_views < 1 || d->max_views > 1024 || d->max_rays < 1))
     return svd_fail(SVD_EINVAL, "serve: max_views must be 1..1024 and max_rays >= 1");
@@ -549,9 +551,12 @@ extern "C" int svd_server_create(svd_world* w, const svd_server_desc* d, svd_ser
     server_release(s);
     return svd_fail(SVD_EDEVICE, "serve: %s", hipGetErrorString(e));
   }
-  if (d->mode == SVD_SERVE_BATCHED) {
+  if (d->mode == SVD_SERVE_BATCHED || d->mode == SVD_SERVE_PLAIN_CONCURRENT) {
+    // concurrent plain launches each trace one request on their flight's own
+    // view table and queue block (a one-view batch area), on its own stream
+    const uint32_t views = d->mode == SVD_SERVE_BATCHED ? d->max_views : 1u;
     for (Flight& f : s->fl) {
-      int rc = svd_batch_create(w, d->max_views, &f.batch);
+      int rc = svd_batch_create(w, views, &f.batch);
       if (rc == SVD_OK && d->tile_w) rc = svd_batch_set_tiling(f.batch, d->tile_w, d->claim ? d->claim : 1);
       if (rc == SVD_OK && d->blocks_per_cu) rc = svd_batch_set_occupancy(f.batch, d->blocks_per_cu);
       if (rc) {

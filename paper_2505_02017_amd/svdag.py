@@ -516,6 +516,7 @@ def svd_batch_tune(b: Batch, cams, out, reps: int = 3, stream=None):
 
 SVD_SERVE_BATCHED = 0
 SVD_SERVE_PLAIN = 1
+SVD_SERVE_PLAIN_CONCURRENT = 2
 
 
 class Server:

@@ -157,14 +157,14 @@ def test_map512_full_frames(env, map512):
     assert len(lods_seen) >= 2
 
 
-def test_map1024_region_full_frame(env):
-    """The 32x32-chunk map of 1024^3 chunks at 2560x1440 (the bench's view 0
-    of it): the 7x7 chunks around the camera hold the map's content and every
-    other chunk is empty (an empty blob in the library's world, no DAG in the
-    oracle's).  Every pixel is compared with the oracle: chunk edge 1024
-    with LODs 1 to 3 picked (7, 6 and 5 internal DAG levels; LOD 0 would need
-    the camera within 256 voxels of a chunk centre, and the single 1024^3
-    terrain chunk covers it)."""
+@pytest.fixture(scope="module")
+def map1024_region(env):
+    """The 32x32-chunk map of 1024^3 chunks, around the bench's view 0: the
+    7x7 chunks around that camera hold the map's content (generated on the
+    GPU, byte-equal to the host generator) and every other chunk is empty (an
+    empty blob in the library's world, no DAG in the oracle's).  The oracle
+    holds LODs 1 to 3 of the real chunks; cameras near view 0 pick only
+    those (LOD 0 needs a chunk centre within 256 voxels)."""
     svdag, torch = env
     sw = scenes.SceneWorld("map1024", 2025)
     CL, S, (gx, gy, gz) = sw.chunk_log2, sw.S, sw.grid
@@ -174,18 +174,15 @@ def test_map1024_region_full_frame(env):
     region = [(cx, cy, 0) for cy in range(max(0, ccy - 3), min(gy, ccy + 4))
               for cx in range(max(0, ccx - 3), min(gx, ccx + 4))]
     ow = oracle.World(CL, sw.grid, 4)
-    fr = oracle.camera_frame(cam)
-    lods = ow.lod_pick(fr.O, thr)
     dev = torch.empty(S ** 3, dtype=torch.uint8, device="cuda")
     work_dev = None
     blobs = {}
 
     def build(c, g):
         ci = c[0] + gx * c[1]
-        k = int(lods[ci])
         b = svdag.svd_chunk_build(g, CL, 4)
-        pyr = oracle.pyramid(g, S, k + 1)
-        return c, ci, b, k, oracle.Dag(pyr[k], S >> k)
+        pyr = oracle.pyramid(g, S, 4)
+        return c, ci, b, [(k, oracle.Dag(pyr[k], S >> k)) for k in (1, 2, 3)]
 
     t0 = time.time()
     with ThreadPoolExecutor(NT) as ex:
@@ -195,20 +192,37 @@ def test_map1024_region_full_frame(env):
                 work_dev = sw.chunk_device(c, dev, work_dev)
                 futs.append(ex.submit(build, c, dev.cpu().numpy()))
             for f in futs:
-                c, ci, b, k, d = f.result()
+                c, ci, b, dags = f.result()
                 blobs[c] = b
-                ow.set_dag(ci, k, d)
+                for k, d in dags:
+                    ow.set_dag(ci, k, d)
     note(f"map1024: {len(region)} chunks around ({ccx}, {ccy}) built in {time.time() - t0:.1f}s")
+    del dev
     empty = svdag.svd_chunk_build(np.zeros(S ** 3, np.uint8), CL, 4)
     nbytes = lambda b: sum((svdag.svd_blob_stats_get(b, k)["device_bytes"] + 255) // 256 * 256 for k in range(4))
     nch = gx * gy * gz
     pool = torch.empty(svdag.table_bytes(sw.grid) + sum(nbytes(b) for b in blobs.values())
                        + nch * (nbytes(empty) + 256), dtype=torch.uint8, device="cuda")
     w = svdag.svd_world_create(svdag.make_desc(CL, sw.grid, 4, thr), pool)
-    for cy in range(gy):
-        for cx in range(gx):
-            svdag.svd_chunk_upload(w, (cx, cy, 0), blobs.get((cx, cy, 0), empty))
+    srcs = {(cx, cy, 0): blobs.get((cx, cy, 0), empty) for cy in range(gy) for cx in range(gx)}
+    for c, b in srcs.items():
+        svdag.svd_chunk_upload(w, c, b)
     torch.cuda.synchronize()
+    yield dict(sw=sw, thr=thr, cam=cam, region=region, ow=ow, w=w, srcs=srcs,
+               region_bytes=sum(nbytes(b) for b in blobs.values()))
+    del pool
+
+
+def test_map1024_region_full_frame(env, map1024_region):
+    """Every pixel of the bench's view 0 of the map (2560x1440) against the
+    oracle: chunk edge 1024 with LODs 1 to 3 picked (7, 6 and 5 internal DAG
+    levels)."""
+    svdag, torch = env
+    m = map1024_region
+    sw, cam, ow, w, thr, region = m["sw"], m["cam"], m["ow"], m["w"], m["thr"], m["region"]
+    gx = sw.grid[0]
+    fr = oracle.camera_frame(cam)
+    lods = ow.lod_pick(fr.O, thr)
     raw, vt = _trace_like_bench(svdag, torch, w, cam)
     assert np.array_equal(vt & 3, lods)
     _properties(svdag, raw, vt, sw)
@@ -219,6 +233,74 @@ def test_map1024_region_full_frame(env):
     seen = set(ref["lod"][ref["hit"] == 1].tolist())
     assert {int(lods[c[0] + gx * c[1]]) for c in region} == {1, 2, 3}
     assert len(seen) >= 2, seen
+
+
+def _region_requests(sw, ow, thr, cam, n, seed):
+    """Requests from cameras around `cam` (within 128 voxels, 50 above the
+    terrain, any heading, pitch in [-20, 5] degrees) that pick no LOD 0,
+    resolutions uniform over 320x180 .. 1920x1080, Poisson arrivals at 200/s."""
+    rng = np.random.default_rng(seed)
+    sizes = ((320, 180), (640, 360), (1280, 720), (1920, 1080))
+    out, t = [], 0.0
+    while len(out) < n:
+        x = float(cam.pos[0]) + rng.uniform(-128, 128)
+        y = float(cam.pos[1]) + rng.uniform(-128, 128)
+        z = min(sw.height(int(x), int(y)) + 50.0, sw.extent[2] - 0.5)
+        yaw, pitch = rng.uniform(0, 2 * np.pi), np.radians(rng.uniform(-20.0, 5.0))
+        d = np.array([np.cos(pitch) * np.cos(yaw), np.cos(pitch) * np.sin(yaw), np.sin(pitch)])
+        W, H = sizes[int(rng.integers(len(sizes)))]
+        c = scenes.Camera((x, y, z), tuple(np.array([x, y, z]) + 100.0 * d), (0.0, 0.0, 1.0), 60.0, W, H).as_f32()
+        if np.any(ow.lod_pick(oracle.camera_frame(c).O, thr) == 0):
+            continue
+        t += rng.exponential(1 / 200.0)
+        out.append((t, c))
+    return out
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_map1024_region_served_sampled(env, map1024_region, mode):
+    """About 50 requests served on the map of 1024^3 chunks through a pool
+    holding a quarter of the region's chunk bytes (streaming uploads),
+    batched or as concurrent per-request launches: every request equals its
+    view traced alone on the full world, and sampled pixels equal the
+    oracle's."""
+    svdag, torch = env
+    m = map1024_region
+    sw, ow, thr, w_full = m["sw"], m["ow"], m["thr"], m["w"]
+    sched = _region_requests(sw, ow, thr, m["cam"], 48, seed=11 + mode)
+    nch = sw.grid[0] * sw.grid[1] * sw.grid[2]
+    budget = m["region_bytes"] // 4 // 256 * 256
+    pool = torch.empty(svdag.table_bytes(sw.grid) + 2 * svdag.batch_bytes(nch, 8) + budget,
+                       dtype=torch.uint8, device="cuda")
+    w = svdag.svd_world_create(svdag.make_desc(sw.chunk_log2, sw.grid, 4, thr), pool)
+    s = svdag.svd_server_create(w, mode=mode, max_views=8 if mode == 0 else 1, inflight=2, max_rays=1 << 23)
+    for c, b in m["srcs"].items():
+        svdag.svd_server_set_chunk(s, c, b)
+    outs = [torch.full((c.width * c.height, 4), -1, dtype=torch.int32, device="cuda") for _, c in sched]
+    torch.cuda.synchronize()
+    note(f"map1024 region: serving {len(sched)} requests (mode {mode}), pool {budget >> 20} of "
+         f"{m['region_bytes'] >> 20} MiB")
+    t0 = time.perf_counter()
+    for i, (t, c) in enumerate(sched):
+        while time.perf_counter() - t0 < t:
+            pass
+        svdag.svd_server_submit(s, c, outs[i], tag=i)
+    done = []
+    while len(done) < len(sched) and time.perf_counter() - t0 < 60:
+        done += svdag.svd_server_poll(s, 256, wait_us=100000)
+    st = svdag.svd_server_stats_get(s)
+    svdag.svd_server_destroy(s)
+    note(f"served: {st}")
+    assert len(done) == len(sched) and all(d["status"] == 0 for d in done)
+    assert st["uploads"] > 0 and st["pool_used"] <= budget
+    rng = np.random.default_rng(5)
+    hits = 0
+    for i, (_, c) in enumerate(sched):
+        got = outs[i].cpu().numpy()
+        alone, _ = _trace_like_bench(svdag, torch, w_full, c)
+        assert np.array_equal(got, alone), f"request {i}"
+        hits += _sampled(svdag, ow, got, c, 1000, f"request {i} ({c.width}x{c.height})", rng)
+    assert hits > 0
     del pool
 
 

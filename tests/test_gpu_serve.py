@@ -1,7 +1,8 @@
 """Per-LOD residency and the request server: a view whose LOD is not loaded
 is marked, never read; every served request equals the same camera traced
-alone on a world with every chunk resident, whether batched or plain, with
-the pool large or too small for the map (forced evictions)."""
+alone on a world with every chunk resident, whether batched or plain (serial
+or concurrent), with the pool large or too small for the map (forced
+evictions)."""
 import time
 
 import numpy as np
@@ -147,6 +148,7 @@ def _serve(svdag, torch, sw, blobs, cams, mode, views, inflight, budget, flags, 
 
 @pytest.mark.parametrize("mode,views,inflight,tight,sf", [(0, 8, 2, False, 0.0), (0, 8, 2, True, 0.0),
                                                           (0, 3, 3, True, 0.0), (1, 1, 3, True, 0.0),
+                                                          (2, 1, 3, True, 0.0), (2, 1, 4, False, 0.0),
                                                           (0, 8, 2, False, 2.0), (0, 4, 2, True, 1.5)])
 def test_server_results_equal_alone(env, world, mode, views, inflight, tight, sf):
     svdag, torch = env
@@ -180,7 +182,7 @@ def test_server_results_equal_alone(env, world, mode, views, inflight, tight, sf
     if total > budget:
         assert st["evictions"] > 0
     n = sw.grid[0] * sw.grid[1] * sw.grid[2]
-    spare = 0 if mode == 0 else inflight * svdag.batch_bytes(n, views)  # plain mode makes no batch areas
+    spare = inflight * svdag.batch_bytes(n, views) if mode == 1 else 0  # serial plain mode makes no batch areas
     assert st["pool_used"] <= budget + spare
     if mode == 0:
         assert st["launches"] <= len(cams)
