@@ -19,11 +19,13 @@
 //
 // The walk is one hierarchy: chunk grid (level chunk_log2, in voxels), the
 // chunk's DAG levels down to 8^3 nodes (level k+3 for LOD k), the 4^3 leaf
-// bitmap (k+2), its 2^3 sub-blocks (k+1) and cells (k).  At a non-empty node
-// the child containing the current instant is found with three mid-plane
-// tests; an empty child is left by one exact step at its level, followed by
-// a pop to the lowest common ancestor of the old and new cells (highest
-// changed coordinate bit).  The node words of the current path live in LDS.
+// bitmap (k+2), its 2^3 sub-blocks (k+1) and cells (k).  Entering a non-empty
+// cell finds its child that holds the current instant with three mid-plane
+// tests; an empty cell is left by one exact step at its level, and the walk
+// goes on at the neighbour: a sibling in the same parent, or the child of
+// the lowest common ancestor of the old and new cells (highest changed
+// coordinate bit) that holds the new cell, found from the coordinates
+// without plane tests.  The node words of the current path live in LDS.
 // Hits are resolved after the loop (DFS index, material run, t, face).
 #include <hip/hip_runtime.h>
 
@@ -143,7 +145,7 @@ struct Ray {
   uint32_t ad[3];   // |D_a|
   uint32_t ad2[3];  // 2 |D_a| (< 2^32)
   uint32_t mm;      // mirror mask (bit a: D_a < 0) = class bits
-  uint32_t Nt, Dt, ph, D2;
+  uint32_t Nt, ph, D2;      // instant Nt / (D2 / 2), phase
   uint64_t T[3];    // 2 Nt |D_a| + 1 + ph - class_a
 
   __host__ __device__ __forceinline__ uint32_t cls(int a) const { return (mm >> a) & 1u; }
@@ -156,20 +158,21 @@ struct Ray {
     const int64_t N = X16 - Om[a];
     return (N < 0) | past_n(a, (uint32_t)N);
   }
-  __host__ __device__ __forceinline__ void set_time(uint32_t n, uint32_t d, uint32_t c) {
+  __host__ __device__ __forceinline__ void set_time(uint32_t n, uint32_t d2, uint32_t c) {
     Nt = n;
-    Dt = d;
     ph = c;
-    D2 = 2u * d;
+    D2 = d2;
     _Pragma("unroll") for (int a = 0; a < 3; a++) T[a] = (uint64_t)n * ad2[a] + (1u + c - cls(a));
   }
 };
 
 // Leave cell c (any level; E its exit-plane numerators): the earliest exit
 // plane sets the ray's new instant and c steps to the neighbour across it (on
-// every axis that ties).  `diff` gets the changed coordinate bits.  False when
-// D == 0: the ray never leaves the cell.
-__host__ __device__ __forceinline__ bool exit_cell(Ray& r, const uint32_t E[3], int32_t c[3], uint32_t& diff) {
+// every axis that ties).  `diff` gets the changed coordinate bits and `step`
+// the axes that stepped (bit a).  False when D == 0: the ray never leaves
+// the cell.
+__host__ __device__ __forceinline__ bool exit_cell(Ray& r, const uint32_t E[3], int32_t c[3], uint32_t& diff,
+                                                   uint32_t& step) {
   // Key of axis a, scaled against axis b: E_a * 2|D_b| + class_a.
   uint32_t bE = E[0], bA2 = r.ad2[0], bC = r.cls(0), sm = 1u;
   _Pragma("unroll") for (int a = 1; a < 3; a++) {
@@ -182,13 +185,14 @@ __host__ __device__ __forceinline__ bool exit_cell(Ray& r, const uint32_t E[3], 
     sm = lt ? (1u << a) : (eq ? sm | (1u << a) : sm);
   }
   if (bA2 == 0) return false;
-  r.set_time(bE, bA2 >> 1, bC);  // |D| of the exit axis (2|D| < 2^32 is exact)
+  r.set_time(bE, bA2, bC);  // 2|D| of the exit axis
   diff = 0;
   _Pragma("unroll") for (int a = 0; a < 3; a++) {
     const uint32_t s = (sm >> a) & 1u;
     diff |= (uint32_t)(c[a] ^ (c[a] + (int32_t)s));
     c[a] += (int32_t)s;
   }
+  step = sm;
   return true;
 }
 
@@ -273,7 +277,7 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
     const uint32_t nb = start << 16;
     if ((uint64_t)nb * d0 > (uint64_t)n0 * mad) { n0 = nb; d0 = mad; c0 = 0; }
   }
-  r.set_time(n0, d0, c0);
+  r.set_time(n0, 2u * d0, c0);
 
   int32_t c[3];
   uint32_t E[3];  // exit-plane numerators of cell c at level lev
@@ -331,52 +335,63 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
       stk[(CL - 3) * ss] = root;
       mask = root >> kPtrBits;
       ptr = 0;
-      // DAG walk inside the chunk, until a hit or the ray leaves the chunk
+      // Into the root's child that holds the current instant.  From here on
+      // c (level lev) is a cell whose parent's children mask is `mask` and
+      // whose octant in that parent is `oct`.
+      uint32_t oct = descend(r, c, E, lev);
+      // DAG walk inside the chunk, until a hit or the ray leaves the chunk.
+      // An iteration enters c and descends one level if c is not empty, then
+      // leaves the cell it is in if that one is empty.  Leaving a cell finds
+      // the next cell without mid-plane tests: a sibling in the same parent
+      // (its octant differs on the stepped axes), or the child of the lowest
+      // common ancestor that holds the new cell (the ancestor's mask comes
+      // from the path stack).  No iteration guard: each exit moves the cell
+      // forward on some axis of the mirrored ray and each descent lowers the
+      // level, so the walk inside a chunk ends whatever the DAG holds.
       for (;;) {
-        uint32_t oct = descend(r, c, E, lev);
-        if ((mask >> oct) & 1u) {
-          if (lev == k) { status = kHit; break; }
+        uint32_t full = (mask >> oct) & 1u;
+        if (full && lev == k) { status = kHit; break; }
+        if (full) {
           enter_child(lev, k, oct, mask, ptr, lmask, bitmap, nodes, leaves, stk, ss);
-          // A second descent in the same iteration: lanes that go on down
-          // use the issue slots in which the lanes leaving an empty cell run
-          // the longer exit path (divergent lanes of a wave run both).
           oct = descend(r, c, E, lev);
-          if ((mask >> oct) & 1u) {
-            if (lev == k) { status = kHit; break; }
-            enter_child(lev, k, oct, mask, ptr, lmask, bitmap, nodes, leaves, stk, ss);
-            continue;
+          full = (mask >> oct) & 1u;
+        }
+        if (!full) {
+          uint32_t diff, step;
+          if (!exit_cell(r, E, c, diff, step)) { status = kMiss; break; }
+          const int pl = lev + (32 - __builtin_clz(diff));  // lowest common ancestor level
+          if (pl > CL) {  // into the next chunk
+            _Pragma("unroll") for (int a = 0; a < 3; a++) {
+              c[a] >>= (CL - lev);
+              E[a] = ((uint32_t)(c[a] + 1) << (CL + 16)) - r.Oml[a];
+            }
+            lev = CL;
+            break;
           }
-        }
-        // the child is empty: leave it through its earliest exit plane (no
-        // iteration guard here: each exit moves the cell forward on some axis
-        // of the mirrored ray and each descent lowers the level, so the walk
-        // inside a chunk ends whatever the DAG holds)
-        uint32_t diff;
-        if (!exit_cell(r, E, c, diff)) { status = kMiss; break; }
-        const int pl = lev + (32 - __builtin_clz(diff));  // lowest common ancestor level
-        if (pl > CL) {  // into the next chunk
-          _Pragma("unroll") for (int a = 0; a < 3; a++) {
-            c[a] >>= (CL - lev);
-            E[a] = ((uint32_t)(c[a] + 1) << (CL + 16)) - r.Oml[a];
+          if (pl == lev + 1) {  // a sibling: one cell on along the stepped axes
+            _Pragma("unroll") for (int a = 0; a < 3; a++) E[a] += ((step >> a) & 1u) << (lev + 16);
+            oct ^= step;
+          } else {
+            // the ancestor's child (level pl - 1) that holds the new cell, with
+            // its exit planes (numerators in [0, 2^32) inside the world)
+            _Pragma("unroll") for (int a = 0; a < 3; a++) {
+              c[a] >>= (pl - 1 - lev);
+              E[a] = ((uint32_t)(c[a] + 1) << (pl - 1 + 16)) - r.Oml[a];
+            }
+            lev = pl - 1;
+            oct = (((uint32_t)c[0] & 1u) | (((uint32_t)c[1] & 1u) << 1) | (((uint32_t)c[2] & 1u) << 2)) ^ r.mm;
+            if (pl >= k + 3) {
+              const uint32_t w = stk[(pl - 3) * ss];
+              mask = w >> kPtrBits;
+              ptr = w & kPtrMask;
+            } else if (pl == k + 2) {
+              mask = lmask;
+            } else {  // pl == k + 1: the sub-block of the leaf
+              const uint32_t o1 = ((((uint32_t)c[0] >> 1) & 1u) | ((((uint32_t)c[1] >> 1) & 1u) << 1) |
+                                   ((((uint32_t)c[2] >> 1) & 1u) << 2)) ^ r.mm;
+              mask = (uint32_t)(bitmap >> (8 * o1)) & 0xFFu;
+            }
           }
-          lev = CL;
-          break;
-        }
-        // exit planes of the ancestor cell (numerators in [0, 2^32) inside the world)
-        _Pragma("unroll") for (int a = 0; a < 3; a++) {
-          c[a] >>= (pl - lev);
-          E[a] = ((uint32_t)(c[a] + 1) << (pl + 16)) - r.Oml[a];
-        }
-        lev = pl;
-        if (lev >= k + 3) {
-          const uint32_t w = stk[(lev - 3) * ss];
-          mask = w >> kPtrBits;
-          ptr = w & kPtrMask;
-        } else if (lev == k + 2) {
-          mask = lmask;
-        } else {
-          const uint32_t o1 = (((uint32_t)c[0] & 1u) | (((uint32_t)c[1] & 1u) << 1) | (((uint32_t)c[2] & 1u) << 2)) ^ r.mm;
-          mask = (uint32_t)(bitmap >> (8 * o1)) & 0xFFu;
         }
       }
       continue;
@@ -384,8 +399,8 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
     }
     // an empty or culled chunk, or one whose solid cells all lie behind the
     // ray: cross it
-    uint32_t diff;
-    if (!exit_cell(r, E, c, diff)) { status = kMiss; break; }
+    uint32_t diff, step;
+    if (!exit_cell(r, E, c, diff, step)) { status = kMiss; break; }
     _Pragma("unroll") for (int a = 0; a < 3; a++) E[a] = ((uint32_t)(c[a] + 1) << (CL + 16)) - r.Oml[a];
   }
 
@@ -419,16 +434,20 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
     }
     const uint32_t mat = ((gptr8)dag->rle_mat)[lo];
     // entry face: lowest axis whose entry plane is crossed at the hit instant
+    // (the direction is recomputed here rather than kept through the walk)
     uint32_t face = 0;
+    double len2 = 0.0;
     _Pragma("unroll") for (int a = 0; a < 3; a++) {
-      if (face || !D[a]) continue;
+      const uint32_t ada = r.ad2[a] >> 1;
+      len2 += (double)ada * (double)ada;
+      if (face || !ada) continue;
       const uint32_t cl = r.cls(a);
       const int64_t X16 = (int64_t)(cl ? h[a] + 1 : h[a]) << (k + 16);
       const int64_t ne = cl ? p.O[a] - X16 : X16 - p.O[a];
-      if (ne >= 0 && cl == r.ph && (uint64_t)ne * r.Dt == (uint64_t)r.Nt * r.ad[a]) face = 1 + 2 * a + cl;
+      if (ne >= 0 && cl == r.ph && (uint64_t)ne * (r.D2 >> 1) == (uint64_t)r.Nt * ada) face = 1 + 2 * a + cl;
     }
-    const double len = sqrt((double)D[0] * D[0] + (double)D[1] * D[1] + (double)D[2] * D[2]);
-    const float t = (float)(((double)r.Nt / (double)r.Dt) * len * (1.0 / 65536.0));
+    const double len = sqrt(len2);
+    const float t = (float)(((double)r.Nt / (double)(r.D2 >> 1)) * len * (1.0 / 65536.0));
     rec.x = ((uint32_t)h[0] << k) | (((uint32_t)h[1] << k) << 16);
     rec.y = ((uint32_t)h[2] << k) | ((uint32_t)k << 16) | (face << 20) | (1u << 23) | (mat << 24);
     rec.z = float_bits(t);
@@ -458,12 +477,13 @@ __device__ __forceinline__ bool take_tiles(uint32_t* queue, uint32_t total, uint
   return false;
 }
 
+// Held to 6 waves per SIMD (80 VGPRs at most; it fits in fewer).
 // Persistent: a machine-filling grid whose waves each take 16x4-pixel tiles
 // from the per-XCD queues until the image is done, so that no wave idles
 // while the slower waves of its work-group finish (ray costs vary widely per
 // tile).  Waves that find every queue dry count themselves out; the last one
 // clears the queues, so every launch starts from zero.
-__global__ __launch_bounds__(kBlock) void trace_kernel(TraceParams p) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 6))) void trace_kernel(TraceParams p) {
   __shared__ uint32_t stk[kStackLevels][kBlock];
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   constexpr uint32_t tw = kViewTileW, th = 64 / kViewTileW;
