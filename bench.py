@@ -59,13 +59,25 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def default_tune_cache():
+    base = os.environ.get("XDG_CACHE_HOME") or os.path.join(os.path.expanduser("~"), ".cache")
+    return os.path.join(base, "paper_2505_02017_amd", "tune.txt")
+
+
+def tune_cache_path(args):
+    """The tuning cache file (its directory created), or None."""
+    if not args.tune_cache or args.tune_cache == "none":
+        return None
+    os.makedirs(os.path.dirname(os.path.abspath(args.tune_cache)), exist_ok=True)
+    return args.tune_cache
+
+
 def counter_profile(workload):
     """Counter-derived figures of the trace kernel from the committed profile
     (profiles/trace_kernel_<workload>_traffic.txt), or {} if that profile was
     taken on a different kernel source than the one built here."""
-    import hashlib
+    from paper_2505_02017_amd.build import kernel_source_hash
     path = os.path.join(ROOT, "profiles", f"trace_kernel_{workload}_traffic.txt")
-    src = os.path.join(ROOT, "paper_2505_02017_amd", "csrc", "kernels.hip")
     if not os.path.exists(path):
         return {}
     vals = {}
@@ -73,8 +85,7 @@ def counter_profile(workload):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.split()[0] if v.split() else ""
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if vals.get("kernel_source_sha256_16") != sha:
+    if vals.get("kernel_source_hash") != kernel_source_hash():
         return {}
     return vals
 
@@ -260,6 +271,8 @@ def main():
     ap.add_argument("--time-budget", type=float, default=540.0,
                     help="seconds the whole run may take: the map1024 leg is skipped (and said so) "
                          "if it would not fit")
+    ap.add_argument("--tune-cache", default=default_tune_cache(),
+                    help="tuning cache file of the per-view and batch tuners ('none': tune every run)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -320,6 +333,12 @@ def main():
     stream = torch.cuda.current_stream()
 
     stage_flags = svdag.SVD_BEAM if args.beam else 0
+    # the per-view tile and occupancy: from the tuning cache, else tuned on
+    # the benchmark's own views (and stored), before the warm-up
+    cache = tune_cache_path(args)
+    tuned = svdag.svd_world_tune(world, frames_gpu, out, stage_flags, reps=3, cache_path=cache, stream=stream)
+    log(f"per-view tile {tuned.tile_w}x{64 // tuned.tile_w}, {tuned.blocks_per_cu} blocks/CU "
+        + ("(from the tuning cache)" if tuned.from_cache else f"(tuned: {tuned.configs_timed} configurations)"))
 
     def step(i, ev=None):
         f = frames_gpu[i % len(frames_gpu)]
@@ -398,6 +417,7 @@ def main():
                      "grays": round(W * H / float(np.percentile(d2h_ms, 50)) / 1e6, 4),
                      "note": "stage + trace + records to pinned host memory (PCIe), not the metric"},
         "hit_fraction": round(float(hits["hit"].mean()), 4),
+        "tuning": {"kernel_hash": svdag.svd_kernel_hash(), "cache": cache, "view": tuned.as_dict()},
     }
 
     if use_oracle:
@@ -519,7 +539,8 @@ def main():
         }
 
     if args.batch_views > 0:
-        result["batched"] = bench_batched(args, sw, world, svdag, torch)
+        result["batched"] = bench_batched(args, sw, world, svdag, torch, cache)
+        result["tuning"]["batch"] = result["batched"].pop("tuning")
     modes = ("batched", "plain", "plain_concurrent")
     if args.serve_seconds > 0:
         # the workload's own map: rates where the walkers outgrow the pool
@@ -557,7 +578,7 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def bench_batched(args, sw, world, svdag, torch):
+def bench_batched(args, sw, world, svdag, torch, cache):
     """A batch of views of mixed resolution over the same world: one
     graph-launched batch (autotuned tiling) against per-view launches."""
     rng = np.random.default_rng([args.seed, 64])
@@ -573,9 +594,10 @@ def bench_batched(args, sw, world, svdag, torch):
     out_p = torch.empty((nrec, 4), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
     batch = svdag.svd_batch_create(world, len(cams))
-    tw, claim, occ, _ = svdag.svd_batch_tune(batch, cams, out_b, reps=3, stream=stream)
-    log(f"batch of {len(cams)} views ({nrec} rays): tuned tile {tw}x{64 // tw}, claim {claim}, "
-        f"{occ} blocks/CU")
+    tuned = svdag.svd_batch_tune_cached(batch, cams, out_b, reps=3, cache_path=cache, stream=stream)
+    tw, claim, occ = tuned.tile_w, tuned.claim, tuned.blocks_per_cu
+    log(f"batch of {len(cams)} views ({nrec} rays): tile {tw}x{64 // tw}, claim {claim}, {occ} blocks/CU "
+        + ("(from the tuning cache)" if tuned.from_cache else f"(tuned: {tuned.configs_timed} configurations)"))
 
     def plain():
         for v, f in enumerate(frames):
@@ -615,6 +637,7 @@ def bench_batched(args, sw, world, svdag, torch):
         "plain_ms_p50": round(float(np.percentile(mp, 50)), 4),
         "plain_ms_p99": round(float(np.percentile(mp, 99)), 4),
         "identical_to_plain": identical,
+        "tuning": tuned.as_dict(),
     }
 
 

@@ -41,6 +41,7 @@ extern "C" {
 #define SVD_EFORMAT (-4)   /* malformed blob bytes */
 #define SVD_ERANGE (-5)    /* value outside the exact-integer range */
 #define SVD_ENOTFOUND (-6) /* chunk not resident */
+#define SVD_EIO (-7)       /* a file could not be written */
 
 /* Trace flags (results are identical with any of them) */
 #define SVD_NO_CULL 1u     /* skip frustum culling */
@@ -260,6 +261,60 @@ int svd_view_trace(svd_world* w, const svd_ray_frame* frame, svd_hit* out_dev, v
 int svd_world_set_occupancy(svd_world* w, uint32_t blocks_per_cu);
 int svd_world_get_occupancy(const svd_world* w, uint32_t* blocks_per_cu, uint32_t* max_per_cu);
 
+/* Wave tile of the per-view beam and trace passes: tile_w x (64/tile_w)
+ * pixels, tile_w in {8, 16, 32, 64} (0 selects the default, 16); anything
+ * else is SVD_EINVAL.  Results do not depend on it. */
+int svd_world_set_tiling(svd_world* w, uint32_t tile_w);
+int svd_world_get_tiling(const svd_world* w, uint32_t* tile_w);
+
+/* Outcome of an autotuning call. */
+typedef struct svd_tune_result {
+  uint32_t tile_w;         /* wave tile width (tile = tile_w x 64/tile_w pixels) */
+  uint32_t claim;          /* tiles per queue access (always 1 for the per-view trace) */
+  uint32_t blocks_per_cu;  /* occupancy of the persistent grid */
+  uint32_t from_cache;     /* 1: taken from the cache file, nothing was timed */
+  float ms;                /* median time of the chosen configuration when it was timed */
+  uint32_t configs_timed;  /* configurations this call timed (0 from the cache) */
+  char key[384];           /* the cache key: device, kernel source hash, workload shape */
+} svd_tune_result;
+
+/* Per-view autotuner: times the whole per-view pass (svd_trace_frame with
+ * `flags`: stage, beam with SVD_BEAM, trace) of every frame in turn, median
+ * of `reps` (1..64) runs after one warm-up, HIP events on `stream`
+ * (synchronises it), for every tile width at the current occupancy, then
+ * every occupancy from the most that fit down to 2 blocks per CU at the best
+ * width; keeps the fastest in the world (svd_world_set_tiling and
+ * svd_world_set_occupancy), so that every later per-view call uses it.
+ * out_dev holds out_records records (at least the largest frame); its
+ * contents are overwritten.
+ *   cache_path (NULL or "" = no cache): a text file of earlier choices keyed
+ *   by this device (architecture, CUs, peak clock), the kernel source hash
+ *   (svd_kernel_hash) and the workload shape (chunk grid, chunk size, LOD
+ *   count, flags, the frames' resolutions and count).  A matching entry is
+ *   applied without timing anything (res->from_cache = 1); otherwise the
+ *   choice is timed and stored (the file is rewritten through a temporary
+ *   and a rename; the directory must exist).  Errors as svd_trace_frame,
+ *   plus SVD_EIO if the cache cannot be written (the tuned configuration is
+ *   applied all the same).  On any other error the world keeps its previous
+ *   tiling and occupancy. */
+int svd_world_tune(svd_world* w, const svd_ray_frame* frames, uint32_t n, svd_hit* out_dev, uint64_t out_records,
+                   uint32_t flags, uint32_t reps, const char* cache_path, void* stream, svd_tune_result* res);
+
+/* The cache file of svd_world_tune and svd_batch_tune_cached, directly.
+ * Lookup: the last entry for `key` into *res (from_cache = 1,
+ * configs_timed = 0); SVD_ENOTFOUND if the file or the entry is missing.
+ * Store: res->key (no tab or line break), tile_w (8/16/32/64), claim
+ * (1..16), blocks_per_cu (>= 1) and ms, replacing any entry of that key;
+ * SVD_EINVAL for a bad entry, SVD_EIO if the file cannot be written.  Other
+ * lines of the file are kept. */
+int svd_tune_cache_lookup(const char* cache_path, const char* key, svd_tune_result* res);
+int svd_tune_cache_store(const char* cache_path, const svd_tune_result* res);
+
+/* Hash of the trace kernels' source this library was built from: the first
+ * 16 hex digits of SHA-256 over kernels.hip followed by svdag_internal.h
+ * ("unknown" if the build did not supply it).  Static string. */
+const char* svd_kernel_hash(void);
+
 /* Per-chunk LOD (bits 0-1), culled (bit 2) and empty (bit 3) flags of the
  * last traced view, copied to host (synchronises `stream`). */
 int svd_view_table(svd_world* w, uint32_t* out, uint32_t n, void* stream);
@@ -331,6 +386,15 @@ int svd_batch_get_tiling(const svd_batch* b, uint32_t* tile_w, uint32_t* claim, 
  * (may be NULL). */
 int svd_batch_tune(svd_batch* b, const svd_camera* cams, uint32_t n, svd_hit* out_dev,
                    uint64_t out_records, uint32_t reps, void* stream, float* best_ms);
+
+/* svd_batch_tune through the cache of svd_world_tune (kind "batch", keyed by
+ * the cameras' resolutions and count): a matching entry sets the batch's
+ * tiling and occupancy without timing; otherwise the batch is tuned and the
+ * choice stored.  Errors as svd_batch_tune, plus SVD_EIO as in
+ * svd_world_tune. */
+int svd_batch_tune_cached(svd_batch* b, const svd_camera* cams, uint32_t n, svd_hit* out_dev,
+                          uint64_t out_records, uint32_t reps, const char* cache_path, void* stream,
+                          svd_tune_result* res);
 
 /* ------------------------------------------------------------------------
  * Serving: view requests of any resolution, arriving at any time, over a

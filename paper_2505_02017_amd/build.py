@@ -1,6 +1,7 @@
 """Build libsvdag.so (hipcc, gfx950) and the scene generator in-tree."""
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -18,7 +19,18 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall", "-pthread"
 # Packed FP32 instructions stay off: some of their forms have returned wrong
 # results on this toolchain without any error.
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["builder.cpp", "runtime.cpp", "server.cpp", "kernels.hip"]
+SOURCES = ["builder.cpp", "runtime.cpp", "server.cpp", "tune.cpp", "kernels.hip"]
+# the sources whose hash keys tuned configurations and kernel profiles
+KERNEL_SOURCES = ["kernels.hip", "svdag_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    """First 16 hex digits of SHA-256 over the kernel sources, in order."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def _run(cmd, verbose):
@@ -37,9 +49,10 @@ def _run(cmd, verbose):
 def build_lib(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
+    define = f'-DSVD_KERNEL_HASH="{kernel_source_hash()}"'
     for src in SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        _run([HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        _run([HIPCC, *COMMON, *DEVICE, define, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
     tmp = LIB + ".tmp"
     _run([HIPCC, *DEVICE, "-shared", "-fPIC", "-pthread", "-o", tmp, *objs], verbose)

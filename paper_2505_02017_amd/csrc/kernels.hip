@@ -478,15 +478,15 @@ __device__ __forceinline__ bool take_tiles(uint32_t* queue, uint32_t total, uint
 }
 
 // Held to 6 waves per SIMD (80 VGPRs at most; it fits in fewer).
-// Persistent: a machine-filling grid whose waves each take 16x4-pixel tiles
-// from the per-XCD queues until the image is done, so that no wave idles
+// Persistent: a machine-filling grid whose waves each take 64-pixel tiles
+// (tile_w x 64/tile_w) from the per-XCD queues until the image is done, so that no wave idles
 // while the slower waves of its work-group finish (ray costs vary widely per
 // tile).  Waves that find every queue dry count themselves out; the last one
 // clears the queues, so every launch starts from zero.
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 6))) void trace_kernel(TraceParams p) {
   __shared__ uint32_t stk[kStackLevels][kBlock];
   const uint32_t tid = threadIdx.x, lane = tid & 63;
-  constexpr uint32_t tw = kViewTileW, th = 64 / kViewTileW;
+  const uint32_t tw = p.tile_w, tw_log2 = __builtin_ctz(p.tile_w), th = 64u >> tw_log2;
   const uint32_t home = blockIdx.x % kQueues;
   uint32_t qi = 0;
   for (;;) {
@@ -498,7 +498,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 6))) 
       break;
     }
     const uint32_t x0 = (t % p.tiles_x) * tw, y0 = (t / p.tiles_x) * th;
-    const uint32_t px = x0 + lane % tw, py = y0 + lane / tw;
+    const uint32_t px = x0 + (lane & (tw - 1)), py = y0 + (lane >> tw_log2);
     uint4* out = reinterpret_cast<uint4*>(p.out);
     const uint32_t start = p.beam ? out[(size_t)y0 * p.W + x0].x : 0u;  // read before the tile is written
     if (px < p.W && py < p.H) out[(size_t)py * p.W + px] = trace_pixel(p, px, py, &stk[0][tid], kBlock, start);

@@ -410,9 +410,9 @@ StageParams world_stage_params(const svd_world* w, const svd_ray_frame* f, bool 
   return sp;
 }
 
-// Per-view beam and trace parameters: 16x4-pixel tiles over the frame, the
-// given view table (per-chunk LOD and flags) and, for the trace, the given
-// queue block.
+// Per-view beam and trace parameters: the world's wave tiles (tile_w x
+// 64/tile_w pixels) over the frame, the given view table (per-chunk LOD and
+// flags) and, for the trace, the given queue block.
 static BeamParams view_beam_params(const svd_world* w, const svd_ray_frame* f, const uint32_t* view, svd_hit* out) {
   BeamParams bp;
   memset(&bp, 0, sizeof(bp));
@@ -422,10 +422,10 @@ static BeamParams view_beam_params(const svd_world* w, const svd_ray_frame* f, c
   memcpy(bp.BY, f->BY, sizeof(bp.BY));
   bp.W = f->width;
   bp.H = f->height;
-  bp.tiles_x = (f->width + kViewTileW - 1) / kViewTileW;
-  const uint64_t th = 64 / kViewTileW;
+  bp.tile_w = w->tile_w;
+  bp.tiles_x = (f->width + bp.tile_w - 1) / bp.tile_w;
+  const uint64_t th = 64 / bp.tile_w;
   bp.total_tiles = (uint32_t)((uint64_t)bp.tiles_x * ((f->height + th - 1) / th));
-  bp.tile_w = kViewTileW;
   memcpy(bp.grid, w->desc.grid, sizeof(bp.grid));
   bp.chunk_log2 = w->desc.chunk_log2;
   bp.view = view;
@@ -446,8 +446,9 @@ static TraceParams view_trace_params(const svd_world* w, const svd_ray_frame* f,
   tp.H = f->height;
   memcpy(tp.grid, w->desc.grid, sizeof(tp.grid));
   tp.chunk_log2 = w->desc.chunk_log2;
-  tp.tiles_x = (f->width + kViewTileW - 1) / kViewTileW;
-  const uint64_t th = 64 / kViewTileW;
+  tp.tile_w = w->tile_w;
+  tp.tiles_x = (f->width + tp.tile_w - 1) / tp.tile_w;
+  const uint64_t th = 64 / tp.tile_w;
   tp.total_tiles = (uint32_t)((uint64_t)tp.tiles_x * ((f->height + th - 1) / th));
   tp.queue = queue;
   tp.view = view;
@@ -517,6 +518,21 @@ extern "C" int svd_world_get_occupancy(const svd_world* w, uint32_t* blocks_per_
   if (!w || !blocks_per_cu || !max_per_cu) return svd_fail(SVD_EINVAL, "svd_world_get_occupancy: null argument");
   *blocks_per_cu = w->per_cu;
   *max_per_cu = w->max_per_cu;
+  return SVD_OK;
+}
+
+extern "C" int svd_world_set_tiling(svd_world* w, uint32_t tile_w) {
+  if (!w) return svd_fail(SVD_EINVAL, "svd_world_set_tiling: null world");
+  if (tile_w == 0) tile_w = kViewTileW;
+  if (!(tile_w == 8 || tile_w == 16 || tile_w == 32 || tile_w == 64))
+    return svd_fail(SVD_EINVAL, "tiling: tile width must be 8, 16, 32 or 64");
+  w->tile_w = tile_w;
+  return SVD_OK;
+}
+
+extern "C" int svd_world_get_tiling(const svd_world* w, uint32_t* tile_w) {
+  if (!w || !tile_w) return svd_fail(SVD_EINVAL, "svd_world_get_tiling: null argument");
+  *tile_w = w->tile_w;
   return SVD_OK;
 }
 
@@ -783,71 +799,6 @@ extern "C" int svd_batch_trace(svd_batch* b, const svd_camera* cams, uint32_t n,
     if (rc) return rc;
   }
   return svd_batch_trace_frames(b, f.data(), n, out_dev, out_records, flags, stream);
-}
-
-// Median time of `reps` batch launches (after one warm-up launch) in the
-// batch's current configuration, HIP events on `s`.
-static int batch_time(svd_batch* b, const svd_camera* cams, uint32_t n, svd_hit* out_dev, uint64_t out_records,
-                      uint32_t reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1, float* med) {
-  std::vector<float> t;
-  for (uint32_t r = 0; r <= reps; r++) {
-    if (hipEventRecord(e0, s) != hipSuccess) return svd_fail(SVD_EDEVICE, "tune: event record failed");
-    int rc = svd_batch_trace(b, cams, n, out_dev, out_records, 0, s);
-    if (rc) return rc;
-    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
-      return svd_fail(SVD_EDEVICE, "tune: sync failed");
-    float ms = 0;
-    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return svd_fail(SVD_EDEVICE, "tune: event timing failed");
-    if (r > 0) t.push_back(ms);
-  }
-  std::sort(t.begin(), t.end());
-  *med = t[t.size() / 2];
-  return SVD_OK;
-}
-
-// Autotuner: time every (tile width, claim) candidate at the current
-// occupancy, then every occupancy from the maximum down to 2 blocks per CU
-// at the best tiling; keep the fastest configuration.
-extern "C" int svd_batch_tune(svd_batch* b, const svd_camera* cams, uint32_t n, svd_hit* out_dev,
-                              uint64_t out_records, uint32_t reps, void* stream, float* best_ms) {
-  if (!b || !cams || n == 0 || reps == 0 || reps > 64) return svd_fail(SVD_EINVAL, "svd_batch_tune: bad argument");
-  hipStream_t s = (hipStream_t)stream;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-    if (e0) (void)hipEventDestroy(e0);
-    return svd_fail(SVD_EDEVICE, "tune: event create failed");
-  }
-  const uint32_t widths[] = {8, 16, 32, 64};
-  const uint32_t claims[] = {1, 2, 4};
-  uint32_t bw = b->tile_w, bc = b->claim, bo = b->per_cu;
-  float best = 3.4e38f;
-  int rc = SVD_OK;
-  for (uint32_t tw : widths) {
-    for (uint32_t cl : claims) {
-      if (rc) break;
-      b->tile_w = tw;
-      b->claim = cl;
-      float med = 0;
-      rc = batch_time(b, cams, n, out_dev, out_records, reps, s, e0, e1, &med);
-      if (rc == SVD_OK && med < best) { best = med; bw = tw; bc = cl; }
-    }
-  }
-  b->tile_w = bw;
-  b->claim = bc;
-  const uint32_t start = b->per_cu;
-  for (uint32_t occ = b->max_per_cu; occ >= 2 && rc == SVD_OK; occ--) {
-    if (occ == start) continue;  // already timed above
-    rc = svd_batch_set_occupancy(b, occ);
-    float med = 0;
-    if (rc == SVD_OK) rc = batch_time(b, cams, n, out_dev, out_records, reps, s, e0, e1, &med);
-    if (rc == SVD_OK && med < best) { best = med; bo = occ; }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  const int rc2 = svd_batch_set_occupancy(b, bo);
-  if (rc == SVD_OK) rc = rc2;
-  if (best_ms) *best_ms = best;
-  return rc;
 }
 
 // ------------------------------------------------- allocation-free batches

@@ -73,7 +73,8 @@ struct TraceParams {
   uint32_t W, H;
   uint32_t grid[3];
   uint32_t chunk_log2;
-  uint32_t tiles_x;       // 16x4-pixel wave tiles per image row
+  uint32_t tile_w;        // wave tile: tile_w x 64/tile_w pixels, tile_w in {8, 16, 32, 64}
+  uint32_t tiles_x;       // wave tiles per image row
   uint32_t total_tiles;
   uint32_t* queue;        // tile queues (see kQueues); all zero between launches
   const uint32_t* view;   // per-chunk view entry
@@ -81,7 +82,7 @@ struct TraceParams {
   svd_hit* out;
   uint32_t beam;          // 1: each tile's first record holds its start bound
 };
-constexpr uint32_t kViewTileW = 16;  // per-view wave tile: 16 x 4 pixels
+constexpr uint32_t kViewTileW = 16;  // default per-view wave tile: 16 x 4 pixels
 
 // Tile queues of the persistent traces: one per XCD (a block's home queue is
 // blockIdx % kQueues, which follows the round-robin placement of blocks on
@@ -244,6 +245,7 @@ struct svd_world {
   uint32_t cus = 0;             // compute units of the device
   uint32_t max_per_cu = 0;      // resident trace blocks per CU at full occupancy
   uint32_t per_cu = 0;          // trace blocks per CU in use (persistent grid = per_cu x cus)
+  uint32_t tile_w = svd::kViewTileW;  // per-view wave tile width (tile = tile_w x 64/tile_w pixels)
   size_t data_begin = 0;
   std::map<size_t, size_t> free_blocks;  // offset -> bytes
   std::vector<Slot> slot;                // [chunk * 4 + lod]

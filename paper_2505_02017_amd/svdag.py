@@ -22,13 +22,15 @@ SVD_EDEVICE = -3
 SVD_EFORMAT = -4
 SVD_ERANGE = -5
 SVD_ENOTFOUND = -6
+SVD_EIO = -7
 SVD_NO_CULL = 1
 SVD_BEAM = 2
 FAULT_CHUNK = 0xFFFFFFFE  # written by the trace if its chunk-walk iteration guard fires (never expected)
 CHUNK_NOT_LOADED = 0xFFFFFFFD  # a ray reached a chunk whose picked LOD is only described
 
 _NAMES = {SVD_EINVAL: "EINVAL", SVD_ENOMEM: "ENOMEM", SVD_EDEVICE: "EDEVICE",
-          SVD_EFORMAT: "EFORMAT", SVD_ERANGE: "ERANGE", SVD_ENOTFOUND: "ENOTFOUND"}
+          SVD_EFORMAT: "EFORMAT", SVD_ERANGE: "ERANGE", SVD_ENOTFOUND: "ENOTFOUND",
+          SVD_EIO: "EIO"}
 
 EXPORTS = [
     "svd_last_error", "svd_chunk_build", "svd_blob_to_bytes", "svd_blob_from_bytes",
@@ -41,6 +43,8 @@ EXPORTS = [
     "svd_batch_set_tiling", "svd_batch_set_occupancy", "svd_batch_get_tiling", "svd_batch_tune",
     "svd_server_create", "svd_server_set_chunk", "svd_server_submit", "svd_server_poll",
     "svd_server_stats_get", "svd_server_destroy", "svd_batch_trace_frames_static",
+    "svd_world_set_tiling", "svd_world_get_tiling", "svd_world_tune", "svd_batch_tune_cached",
+    "svd_kernel_hash", "svd_tune_cache_lookup", "svd_tune_cache_store",
 ]
 
 
@@ -83,6 +87,18 @@ class svd_server_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "submitted", "completed", "failed", "launches", "uploads", "upload_bytes", "evictions",
         "evict_bytes", "memory_waits", "pool_used", "prefetches", "prefetch_bytes")]
+
+
+class svd_tune_result(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_uint32), ("claim", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
+                ("from_cache", ctypes.c_uint32), ("ms", ctypes.c_float), ("configs_timed", ctypes.c_uint32),
+                ("key", ctypes.c_char * 384)]
+
+    def as_dict(self) -> dict:
+        return {"tile": f"{self.tile_w}x{64 // self.tile_w}", "claim": self.claim,
+                "blocks_per_cu": self.blocks_per_cu, "from_cache": bool(self.from_cache),
+                "ms": round(float(self.ms), 4), "configs_timed": self.configs_timed,
+                "key": self.key.decode()}
 
 
 class svd_blob_stats(ctypes.Structure):
@@ -149,6 +165,15 @@ def lib() -> ctypes.CDLL:
         L.svd_batch_tune.argtypes = [vp, ctypes.POINTER(svd_camera), u32, vp, u64, u32, vp,
                                      ctypes.POINTER(ctypes.c_float)]
         L.svd_batch_trace_frames_static.argtypes = [vp, ctypes.POINTER(svd_ray_frame), u32, vp, u64, u32, vp]
+        L.svd_world_set_tiling.argtypes = [vp, u32]
+        L.svd_world_get_tiling.argtypes = [vp, ctypes.POINTER(u32)]
+        L.svd_world_tune.argtypes = [vp, ctypes.POINTER(svd_ray_frame), u32, vp, u64, u32, u32, ctypes.c_char_p,
+                                     vp, ctypes.POINTER(svd_tune_result)]
+        L.svd_batch_tune_cached.argtypes = [vp, ctypes.POINTER(svd_camera), u32, vp, u64, u32, ctypes.c_char_p,
+                                            vp, ctypes.POINTER(svd_tune_result)]
+        L.svd_kernel_hash.argtypes = []
+        L.svd_tune_cache_lookup.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(svd_tune_result)]
+        L.svd_tune_cache_store.argtypes = [ctypes.c_char_p, ctypes.POINTER(svd_tune_result)]
         L.svd_server_create.argtypes = [vp, ctypes.POINTER(svd_server_desc), ctypes.POINTER(vp)]
         L.svd_server_set_chunk.argtypes = [vp, ctypes.POINTER(u32), vp]
         L.svd_server_submit.argtypes = [vp, ctypes.POINTER(svd_camera), vp, u32, u64]
@@ -158,8 +183,9 @@ def lib() -> ctypes.CDLL:
         L.svd_server_destroy.restype = None
         for n in EXPORTS:
             if n not in ("svd_last_error", "svd_blob_free", "svd_free", "svd_world_destroy",
-                         "svd_batch_destroy", "svd_server_destroy"):
+                         "svd_batch_destroy", "svd_server_destroy", "svd_kernel_hash"):
                 getattr(L, n).restype = i32
+        L.svd_kernel_hash.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -408,6 +434,51 @@ def svd_world_get_occupancy(w: World):
     return cur.value, mx.value
 
 
+def svd_world_set_tiling(w: World, tile_w: int):
+    _check(lib().svd_world_set_tiling(w.ptr, tile_w))
+
+
+def svd_world_get_tiling(w: World) -> int:
+    """Wave tile width of the per-view passes (tile = tile_w x 64/tile_w)."""
+    tw = ctypes.c_uint32()
+    _check(lib().svd_world_get_tiling(w.ptr, ctypes.byref(tw)))
+    return tw.value
+
+
+def svd_world_tune(w: World, frames, out, flags: int = 0, reps: int = 3, cache_path=None,
+                   stream=None) -> "svd_tune_result":
+    """Autotune the per-view tile and occupancy on these frames (see
+    svd_world_tune in svdag.h); cache_path None: no cache."""
+    arr = (svd_ray_frame * len(frames))(*frames)
+    assert out.is_cuda and out.is_contiguous()
+    res = svd_tune_result()
+    _check(lib().svd_world_tune(w.ptr, arr, len(frames), ctypes.c_void_p(out.data_ptr()),
+                                out.numel() * out.element_size() // 16, flags, reps, _cache_arg(cache_path),
+                                _stream_ptr(stream), ctypes.byref(res)))
+    return res
+
+
+def svd_tune_cache_lookup(cache_path, key: str):
+    """The cached entry for `key` (svd_tune_result), or None."""
+    res = svd_tune_result()
+    rc = lib().svd_tune_cache_lookup(os.fsencode(cache_path), key.encode(), ctypes.byref(res))
+    if rc == SVD_ENOTFOUND:
+        return None
+    _check(rc)
+    return res
+
+
+def svd_tune_cache_store(cache_path, key: str, tile_w: int, claim: int, blocks_per_cu: int, ms: float = 0.0):
+    res = svd_tune_result(tile_w=tile_w, claim=claim, blocks_per_cu=blocks_per_cu, ms=ms)
+    res.key = key.encode()
+    _check(lib().svd_tune_cache_store(os.fsencode(cache_path), ctypes.byref(res)))
+
+
+def svd_kernel_hash() -> str:
+    """Kernel source hash the loaded library was built from."""
+    return lib().svd_kernel_hash().decode()
+
+
 def svd_view_table(w: World, stream=None) -> np.ndarray:
     out = np.zeros(w.nchunks, np.uint32)
     _check(lib().svd_view_table(w.ptr, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
@@ -498,6 +569,20 @@ def svd_batch_get_tiling(b: Batch):
     tw, cl, oc = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
     _check(lib().svd_batch_get_tiling(b.ptr, ctypes.byref(tw), ctypes.byref(cl), ctypes.byref(oc)))
     return tw.value, cl.value, oc.value
+
+
+def _cache_arg(cache_path):
+    return None if not cache_path else os.fsencode(cache_path)
+
+
+def svd_batch_tune_cached(b: Batch, cams, out, reps: int = 3, cache_path=None, stream=None) -> svd_tune_result:
+    """svd_batch_tune through the tuning cache file (None: no cache)."""
+    arr = _cam_array(cams)
+    ptr, cap = _batch_out(out)
+    res = svd_tune_result()
+    _check(lib().svd_batch_tune_cached(b.ptr, arr, len(cams), ptr, cap, reps, _cache_arg(cache_path),
+                                       _stream_ptr(stream), ctypes.byref(res)))
+    return res
 
 
 def svd_batch_tune(b: Batch, cams, out, reps: int = 3, stream=None):

@@ -2,6 +2,7 @@
 queue): every view's records equal those of its own per-view launch and
 the oracle's, for every tiling, across repeated graph replays."""
 import os
+import re
 
 import numpy as np
 import pytest
@@ -163,4 +164,88 @@ def test_occupancy_does_not_change_results(env, world):
             svdag.svd_world_set_occupancy(w, wmx + 1)
         assert e.value.code == svdag.SVD_EINVAL
     finally:
+        svdag.svd_world_set_occupancy(w, 0)
+
+
+def _per_view_flags(svdag, torch, w, cams, flags):
+    outs = []
+    for c in cams:
+        o = torch.full((c.width * c.height, 4), -1, dtype=torch.int32, device="cuda")
+        svdag.svd_trace_view(w, svdag.to_camera(c), o, flags)
+        outs.append(o)
+    torch.cuda.synchronize()
+    return np.concatenate([o.cpu().numpy() for o in outs])
+
+
+def test_per_view_tilings_and_tuning_cache(env, world, tmp_path):
+    """The per-view tile (8x8, 16x4, 32x2, 64x1) changes the schedule only,
+    with and without the beam pass; the per-view and batch tuners apply
+    their choice, store it in the cache file and take it from there on the
+    next call without timing."""
+    svdag, torch = env
+    sw, w, ow = world
+    cams = _cams(sw, 7, 8)
+    ref = _per_view(svdag, torch, w, cams)                     # default tile 16x4
+    frames = [svdag.svd_camera_frame(svdag.to_camera(c)) for c in cams]
+    assert svdag.svd_world_get_tiling(w) == 16
+    path = str(tmp_path / "tune.txt")
+    try:
+        for tw in (8, 16, 32, 64):
+            svdag.svd_world_set_tiling(w, tw)
+            assert svdag.svd_world_get_tiling(w) == tw
+            for flags in (0, svdag.SVD_BEAM):
+                note(f"per-view tile {tw}x{64 // tw} flags {flags}")
+                assert np.array_equal(_per_view_flags(svdag, torch, w, cams, flags), ref), (tw, flags)
+        with pytest.raises(svdag.SvdError) as e:
+            svdag.svd_world_set_tiling(w, 12)
+        assert e.value.code == svdag.SVD_EINVAL
+        svdag.svd_world_set_tiling(w, 0)
+        assert svdag.svd_world_get_tiling(w) == 16
+
+        big = torch.empty((max(c.width * c.height for c in cams), 4), dtype=torch.int32, device="cuda")
+        with pytest.raises(svdag.SvdError) as e:                 # output smaller than the largest frame
+            svdag.svd_world_tune(w, frames, big[:-1], reps=1, cache_path=path)
+        assert e.value.code == svdag.SVD_EINVAL
+        assert not os.path.exists(path)
+        note("per-view tuner, cache miss")
+        r1 = svdag.svd_world_tune(w, frames, big, svdag.SVD_BEAM, reps=2, cache_path=path)
+        key = r1.key.decode()
+        assert not r1.from_cache and r1.configs_timed >= 4 and r1.ms > 0
+        assert r1.tile_w in (8, 16, 32, 64) and r1.claim == 1
+        assert re.match(r"dev=gfx\S*/\d+cu/\d+mhz kernel=%s kind=view cl=6 grid=4x4x2 lods=4 flags=2 views=8 res="
+                        % svdag.svd_kernel_hash(), key), key
+        assert svdag.svd_world_get_tiling(w) == r1.tile_w
+        assert svdag.svd_world_get_occupancy(w)[0] == r1.blocks_per_cu
+        assert np.array_equal(_per_view_flags(svdag, torch, w, cams, svdag.SVD_BEAM), ref)
+        svdag.svd_world_set_tiling(w, 0)
+        svdag.svd_world_set_occupancy(w, 0)
+        note("per-view tuner, cache hit")
+        r2 = svdag.svd_world_tune(w, frames, big, svdag.SVD_BEAM, reps=2, cache_path=path)
+        assert r2.from_cache and r2.configs_timed == 0 and r2.key.decode() == key
+        assert (r2.tile_w, r2.blocks_per_cu) == (r1.tile_w, r1.blocks_per_cu)
+        assert svdag.svd_world_get_tiling(w) == r1.tile_w
+        assert svdag.svd_world_get_occupancy(w)[0] == r1.blocks_per_cu
+        # other flags are another workload
+        r3 = svdag.svd_world_tune(w, frames, big, 0, reps=1, cache_path=path)
+        assert not r3.from_cache and "flags=0 " in r3.key.decode()
+
+        note("batch tuner through the cache")
+        b = svdag.svd_batch_create(w, len(cams))
+        out = torch.empty((svdag.batch_records(cams), 4), dtype=torch.int32, device="cuda")
+        rb1 = svdag.svd_batch_tune_cached(b, cams, out, reps=1, cache_path=path)
+        assert not rb1.from_cache and "kind=batch" in rb1.key.decode()
+        svdag.svd_batch_set_tiling(b, 16, 1)
+        svdag.svd_batch_set_occupancy(b, 0)
+        rb2 = svdag.svd_batch_tune_cached(b, cams, out, reps=1, cache_path=path)
+        assert rb2.from_cache and (rb2.tile_w, rb2.claim, rb2.blocks_per_cu) == \
+            (rb1.tile_w, rb1.claim, rb1.blocks_per_cu)
+        assert svdag.svd_batch_get_tiling(b) == (rb1.tile_w, rb1.claim, rb1.blocks_per_cu)
+        out.fill_(-1)
+        svdag.svd_batch_trace(b, cams, out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref)
+        svdag.svd_batch_destroy(b)
+        assert len(open(path).read().splitlines()) == 4          # header + view x2 + batch
+    finally:
+        svdag.svd_world_set_tiling(w, 0)
         svdag.svd_world_set_occupancy(w, 0)

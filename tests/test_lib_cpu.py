@@ -192,3 +192,55 @@ def test_gpu_scene_generator_host_contract():
     assert L.sgg_gen_chunk(ipn, dp, 1, 10, 0, 0, 0, None, 0, None, None, 0, None) == -1
     assert L.sgg_gen_chunk(ip, dp, 1, 10, 0, 0, 0, None, 0, None, None, 0, None) == -1
     assert L.sgg_gen_chunk(ip, dp, 1, 11, 0, 0, 0, None, 0, None, None, 0, None) == -1
+
+
+def test_kernel_hash_is_the_built_sources():
+    """The library reports the hash of the kernel sources it was built from;
+    the tuning cache and the kernel profiles are keyed by it."""
+    svdag = _svdag()
+    from paper_2505_02017_amd import build
+    h = svdag.svd_kernel_hash()
+    assert re.fullmatch(r"[0-9a-f]{16}", h)
+    assert h == build.kernel_source_hash(), "library older than its kernel sources: rebuild"
+
+
+def test_tune_cache_file(tmp_path):
+    svdag = _svdag()
+    path = str(tmp_path / "tune.txt")
+    k1 = "dev=gfx950:sramecc+:xnack-/256cu/2400mhz kernel=0123456789abcdef kind=view cl=9 grid=16x16x2 lods=4 flags=0 views=4 res=2560x1440*4"
+    k2 = k1.replace("kind=view", "kind=batch")
+    assert svdag.svd_tune_cache_lookup(path, k1) is None          # no file yet
+    svdag.svd_tune_cache_store(path, k1, 16, 1, 6, 0.5)
+    svdag.svd_tune_cache_store(path, k2, 8, 2, 5, 1.25)
+    r = svdag.svd_tune_cache_lookup(path, k1)
+    assert (r.tile_w, r.claim, r.blocks_per_cu, r.from_cache, r.configs_timed) == (16, 1, 6, 1, 0)
+    assert abs(r.ms - 0.5) < 1e-6 and r.key.decode() == k1
+    assert svdag.svd_tune_cache_lookup(path, k2).as_dict()["tile"] == "8x8"
+    # a prefix of a key is another key
+    assert svdag.svd_tune_cache_lookup(path, k1[:-1]) is None
+    # replacing an entry keeps the others, and one line per key
+    svdag.svd_tune_cache_store(path, k1, 32, 1, 4, 0.4)
+    assert svdag.svd_tune_cache_lookup(path, k1).tile_w == 32
+    assert svdag.svd_tune_cache_lookup(path, k2).tile_w == 8
+    lines = open(path).read().splitlines()
+    assert lines[0].startswith("#") and len(lines) == 3
+    assert lines[-1] == k1 + "\t32 1 4 0.4000"
+    # hand-written and malformed lines are kept and skipped
+    with open(path, "a") as f:
+        f.write("garbage line\n" + k2 + "\tnot numbers\n")
+    assert svdag.svd_tune_cache_lookup(path, k2).tile_w == 8
+    svdag.svd_tune_cache_store(path, k1, 64, 1, 2)
+    assert "garbage line" in open(path).read()
+    # bad entries are refused and leave the file alone
+    before = open(path).read()
+    for bad in ((k1, 12, 1, 6), (k1, 16, 0, 6), (k1, 16, 17, 6), (k1, 16, 1, 0), ("a\tb", 16, 1, 6),
+                ("", 16, 1, 6)):
+        with pytest.raises(svdag.SvdError) as e:
+            svdag.svd_tune_cache_store(path, *bad)
+        assert e.value.code == svdag.SVD_EINVAL
+    assert open(path).read() == before
+    # a directory that does not exist cannot be written
+    with pytest.raises(svdag.SvdError) as e:
+        svdag.svd_tune_cache_store(str(tmp_path / "no" / "tune.txt"), k1, 16, 1, 6)
+    assert e.value.code == svdag.SVD_EIO
+    assert not [p for p in os.listdir(tmp_path) if ".tmp." in p]
