@@ -273,6 +273,9 @@ def main():
                          "if it would not fit")
     ap.add_argument("--tune-cache", default=default_tune_cache(),
                     help="tuning cache file of the per-view and batch tuners ('none': tune every run)")
+    ap.add_argument("--view-tile", type=int, default=0, choices=(0, 8, 16, 32, 64),
+                    help="per-view tile width (with --view-occupancy: no tuning; 0 = tuned)")
+    ap.add_argument("--view-occupancy", type=int, default=0, help="per-view trace blocks per CU (0 = tuned)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -336,9 +339,17 @@ def main():
     # the per-view tile and occupancy: from the tuning cache, else tuned on
     # the benchmark's own views (and stored), before the warm-up
     cache = tune_cache_path(args)
-    tuned = svdag.svd_world_tune(world, frames_gpu, out, stage_flags, reps=3, cache_path=cache, stream=stream)
-    log(f"per-view tile {tuned.tile_w}x{64 // tuned.tile_w}, {tuned.blocks_per_cu} blocks/CU "
-        + ("(from the tuning cache)" if tuned.from_cache else f"(tuned: {tuned.configs_timed} configurations)"))
+    if args.view_tile and args.view_occupancy:
+        svdag.svd_world_set_tiling(world, args.view_tile)
+        svdag.svd_world_set_occupancy(world, args.view_occupancy)
+        view_tuning = {"tile": f"{args.view_tile}x{64 // args.view_tile}", "blocks_per_cu": args.view_occupancy,
+                       "from_cache": False, "fixed": True}
+        log(f"per-view tile {args.view_tile}x{64 // args.view_tile}, {args.view_occupancy} blocks/CU (fixed)")
+    else:
+        tuned = svdag.svd_world_tune(world, frames_gpu, out, stage_flags, reps=3, cache_path=cache, stream=stream)
+        view_tuning = tuned.as_dict()
+        log(f"per-view tile {tuned.tile_w}x{64 // tuned.tile_w}, {tuned.blocks_per_cu} blocks/CU "
+            + ("(from the tuning cache)" if tuned.from_cache else f"(tuned: {tuned.configs_timed} configurations)"))
 
     def step(i, ev=None):
         f = frames_gpu[i % len(frames_gpu)]
@@ -417,7 +428,7 @@ def main():
                      "grays": round(W * H / float(np.percentile(d2h_ms, 50)) / 1e6, 4),
                      "note": "stage + trace + records to pinned host memory (PCIe), not the metric"},
         "hit_fraction": round(float(hits["hit"].mean()), 4),
-        "tuning": {"kernel_hash": svdag.svd_kernel_hash(), "cache": cache, "view": tuned.as_dict()},
+        "tuning": {"kernel_hash": svdag.svd_kernel_hash(), "cache": cache, "view": view_tuning},
     }
 
     if use_oracle:

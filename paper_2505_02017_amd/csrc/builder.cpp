@@ -569,8 +569,28 @@ int derive_device(LodData& L, std::vector<uint8_t>& image) {
   L.off_nodes = put(nodes.data(), nodes.size() * 4);
   L.off_pre = put(pre.data(), pre.size() * 4);
   L.off_leaves = put(L.leaves.data(), L.leaves.size() * 8);
-  L.off_rle_start = put(L.rle_start.data(), L.rle_start.size() * 4);
-  L.off_rle_mat = put(L.rle_mat.data(), L.rle_mat.size());
+  // runs: starts then materials, one section; then the run directory
+  const size_t nr = L.rle_start.size();
+  std::vector<uint8_t> runs(nr * 5);
+  if (nr) {
+    memcpy(runs.data(), L.rle_start.data(), nr * 4);
+    memcpy(runs.data() + nr * 4, L.rle_mat.data(), nr);
+  }
+  L.off_rle_start = put(runs.data(), runs.size());
+  std::vector<uint32_t> dir;
+  if (nr) {
+    const uint32_t B = run_dir_shift((uint32_t)nr, L.n_solid);
+    const uint32_t nd = ((L.n_solid - 1) >> B) + 1;
+    dir.resize((size_t)nd + 1);
+    uint32_t q = 0;
+    for (uint32_t j = 0; j < nd; j++) {
+      const uint64_t first = (uint64_t)j << B;
+      while (q + 1 < nr && L.rle_start[q + 1] <= first) q++;
+      dir[j] = q;
+    }
+    dir[nd] = (uint32_t)nr - 1;
+  }
+  L.off_rle_dir = put(dir.data(), dir.size() * 4);
   align(256);
   L.off_end = image.size();
   return SVD_OK;

@@ -22,11 +22,13 @@
 // bitmap (k+2), its 2^3 sub-blocks (k+1) and cells (k).  Entering a non-empty
 // cell finds its child that holds the current instant with three mid-plane
 // tests; an empty cell is left by one exact step at its level, and the walk
-// goes on at the neighbour: a sibling in the same parent, or the child of
-// the lowest common ancestor of the old and new cells (highest changed
-// coordinate bit) that holds the new cell, found from the coordinates
-// without plane tests.  The node words of the current path live in LDS.
-// Hits are resolved after the loop (DFS index, material run, t, face).
+// goes on at the neighbour: a sibling in the same parent (when the cell was
+// the lower of its pair on every stepped axis, read off its octant), or the
+// child of the lowest common ancestor of the old and new cells (highest
+// changed coordinate bit) that holds the new cell, found from the
+// coordinates without plane tests.  The node words of the current path live
+// in LDS.  Hits are resolved after the loop (DFS index, material run through
+// the run directory, t, face).
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -166,13 +168,11 @@ struct Ray {
   }
 };
 
-// Leave cell c (any level; E its exit-plane numerators): the earliest exit
-// plane sets the ray's new instant and c steps to the neighbour across it (on
-// every axis that ties).  `diff` gets the changed coordinate bits and `step`
-// the axes that stepped (bit a).  False when D == 0: the ray never leaves
-// the cell.
-__host__ __device__ __forceinline__ bool exit_cell(Ray& r, const uint32_t E[3], int32_t c[3], uint32_t& diff,
-                                                   uint32_t& step) {
+// Leave the current cell (any level; E its exit-plane numerators): the
+// earliest exit plane sets the ray's new instant.  `step` gets the axes that
+// step (bit a; every axis that ties).  False when D == 0: the ray never
+// leaves the cell.
+__host__ __device__ __forceinline__ bool exit_cell(Ray& r, const uint32_t E[3], uint32_t& step) {
   // Key of axis a, scaled against axis b: E_a * 2|D_b| + class_a.
   uint32_t bE = E[0], bA2 = r.ad2[0], bC = r.cls(0), sm = 1u;
   _Pragma("unroll") for (int a = 1; a < 3; a++) {
@@ -186,12 +186,6 @@ __host__ __device__ __forceinline__ bool exit_cell(Ray& r, const uint32_t E[3], 
   }
   if (bA2 == 0) return false;
   r.set_time(bE, bA2, bC);  // 2|D| of the exit axis
-  diff = 0;
-  _Pragma("unroll") for (int a = 0; a < 3; a++) {
-    const uint32_t s = (sm >> a) & 1u;
-    diff |= (uint32_t)(c[a] ^ (c[a] + (int32_t)s));
-    c[a] += (int32_t)s;
-  }
   step = sm;
   return true;
 }
@@ -338,6 +332,7 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
       // Into the root's child that holds the current instant.  From here on
       // c (level lev) is a cell whose parent's children mask is `mask` and
       // whose octant in that parent is `oct`.
+      lev = CL;
       uint32_t oct = descend(r, c, E, lev);
       // DAG walk inside the chunk, until a hit or the ray leaves the chunk.
       // An iteration enters c and descends one level if c is not empty, then
@@ -357,28 +352,35 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
           full = (mask >> oct) & 1u;
         }
         if (!full) {
-          uint32_t diff, step;
-          if (!exit_cell(r, E, c, diff, step)) { status = kMiss; break; }
-          const int pl = lev + (32 - __builtin_clz(diff));  // lowest common ancestor level
-          if (pl > CL) {  // into the next chunk
+          uint32_t step;
+          if (!exit_cell(r, E, step)) { status = kMiss; break; }
+          if (((oct ^ r.mm) & step) == 0) {
+            // the cell was the lower of its pair on every stepped axis: the
+            // new cell is its sibling, one cell on along those axes
             _Pragma("unroll") for (int a = 0; a < 3; a++) {
-              c[a] >>= (CL - lev);
-              E[a] = ((uint32_t)(c[a] + 1) << (CL + 16)) - r.Oml[a];
+              const uint32_t s = (step >> a) & 1u;
+              E[a] += s << (lev + 16);
+              c[a] += (int32_t)s;
             }
-            lev = CL;
-            break;
-          }
-          if (pl == lev + 1) {  // a sibling: one cell on along the stepped axes
-            _Pragma("unroll") for (int a = 0; a < 3; a++) E[a] += ((step >> a) & 1u) << (lev + 16);
             oct ^= step;
           } else {
-            // the ancestor's child (level pl - 1) that holds the new cell, with
-            // its exit planes (numerators in [0, 2^32) inside the world)
+            // the lowest common ancestor of the old and new cells is the
+            // level above the highest changed coordinate bit; the new cell
+            // lies in its child at level nl (or in the next chunk, level CL)
+            uint32_t diff = 0;
             _Pragma("unroll") for (int a = 0; a < 3; a++) {
-              c[a] >>= (pl - 1 - lev);
-              E[a] = ((uint32_t)(c[a] + 1) << (pl - 1 + 16)) - r.Oml[a];
+              const int32_t n = c[a] + (int32_t)((step >> a) & 1u);
+              diff |= (uint32_t)(c[a] ^ n);
+              c[a] = n;
             }
-            lev = pl - 1;
+            const int pl = lev + (32 - __builtin_clz(diff));
+            const int nl = pl > CL ? CL : pl - 1;
+            _Pragma("unroll") for (int a = 0; a < 3; a++) {
+              c[a] >>= (nl - lev);
+              E[a] = ((uint32_t)(c[a] + 1) << (nl + 16)) - r.Oml[a];
+            }
+            if (pl > CL) break;  // into the next chunk (level CL)
+            lev = nl;
             oct = (((uint32_t)c[0] & 1u) | (((uint32_t)c[1] & 1u) << 1) | (((uint32_t)c[2] & 1u) << 2)) ^ r.mm;
             if (pl >= k + 3) {
               const uint32_t w = stk[(pl - 3) * ss];
@@ -399,9 +401,13 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
     }
     // an empty or culled chunk, or one whose solid cells all lie behind the
     // ray: cross it
-    uint32_t diff, step;
-    if (!exit_cell(r, E, c, diff, step)) { status = kMiss; break; }
-    _Pragma("unroll") for (int a = 0; a < 3; a++) E[a] = ((uint32_t)(c[a] + 1) << (CL + 16)) - r.Oml[a];
+    uint32_t step;
+    if (!exit_cell(r, E, step)) { status = kMiss; break; }
+    _Pragma("unroll") for (int a = 0; a < 3; a++) {
+      const uint32_t s = (step >> a) & 1u;
+      E[a] += s << (CL + 16);
+      c[a] += (int32_t)s;
+    }
   }
 
   uint4 rec = make_uint4(0u, 0u, 0x7F800000u /* +inf */, 0xFFFFFFFFu);
@@ -425,14 +431,17 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
     const uint32_t o1 = ((h[0] >> 1) & 1) | (((h[1] >> 1) & 1) << 1) | (((h[2] >> 1) & 1) << 2);
     const uint32_t o0 = (h[0] & 1) | ((h[1] & 1) << 1) | ((h[2] & 1) << 2);
     dfs += (uint32_t)__builtin_popcountll(bitmap & ((1ull << (8 * o1 + o0)) - 1ull));
-    // material: the last run starting at or before the DFS index
+    // material: the last run starting at or before the DFS index, searched
+    // between the two run-directory entries around it
     const gptr32 rs = (gptr32)dag->rle_start;
-    uint32_t lo = 0, hi = dag->rle_n;
+    const uint32_t nr = dag->rle_n;
+    const gptr32 dir = (gptr32)dag->rle_dir + (dfs >> run_dir_shift(nr, dag->solid));
+    uint32_t lo = dir[0], hi = dir[1] + 1u;
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
       if (rs[mid] <= dfs) lo = mid; else hi = mid;
     }
-    const uint32_t mat = ((gptr8)dag->rle_mat)[lo];
+    const uint32_t mat = ((gptr8)(rs + nr))[lo];
     // entry face: lowest axis whose entry plane is crossed at the hit instant
     // (the direction is recomputed here rather than kept through the walk)
     uint32_t face = 0;

@@ -206,7 +206,7 @@ static DevDag lod_desc(const svd_world* w, const svd_blob* b, uint32_t k, bool l
     d.leaves = base + L.off_leaves;
     d.pre = base + L.off_pre;
     d.rle_start = base + L.off_rle_start;
-    d.rle_mat = base + L.off_rle_mat;
+    d.rle_dir = base + L.off_rle_dir;
   }
   d.rle_n = (uint32_t)L.rle_start.size();
   d.root = L.root_word;
@@ -249,7 +249,7 @@ int world_upload_lods(svd_world* w, uint32_t ci, const svd_blob* b, uint32_t mas
       d[k].leaves = w->h_desc[base + k].leaves;
       d[k].pre = w->h_desc[base + k].pre;
       d[k].rle_start = w->h_desc[base + k].rle_start;
-      d[k].rle_mat = w->h_desc[base + k].rle_mat;
+      d[k].rle_dir = w->h_desc[base + k].rle_dir;
     }
   }
   int rc = e == hipSuccess ? launch_set_desc(w->d_desc + base, d, 4, s)
@@ -284,7 +284,7 @@ int world_evict_lods(svd_world* w, uint32_t ci, uint32_t mask, hipStream_t s) {
   for (uint32_t k = 0; k < 4; k++) {
     d[k] = w->h_desc[base + k];
     if (k < nl && ((mask >> k) & 1) && w->slot[base + k].state == svd_world::kResident) {
-      d[k].nodes = d[k].leaves = d[k].pre = d[k].rle_start = d[k].rle_mat = 0;
+      d[k].nodes = d[k].leaves = d[k].pre = d[k].rle_start = d[k].rle_dir = 0;
       change = true;
     }
   }

@@ -29,8 +29,8 @@ struct alignas(64) DevDag {
   uint64_t nodes;      // device address: u32 child words
   uint64_t leaves;     // device address: u64 leaf bitmaps
   uint64_t pre;        // device address: u32 prefix counts, parallel to nodes
-  uint64_t rle_start;  // device address: u32 run starts (DFS index)
-  uint64_t rle_mat;    // device address: u8 run materials
+  uint64_t rle_start;  // device address: u32 run starts (DFS index), then the u8 run materials
+  uint64_t rle_dir;    // device address: u32 run directory (see kRunDir)
   uint32_t rle_n;      // number of runs
   uint32_t root;       // child word of the root: (root mask << 24) | 0
   uint32_t solid;      // solid cells at this LOD (0 = empty)
@@ -38,6 +38,16 @@ struct alignas(64) DevDag {
   uint16_t hi[3];
 };
 static_assert(sizeof(DevDag) == 64, "DevDag must stay 64 bytes");
+
+// Run directory: with B = max(0, clz(rle_n) - clz(solid)), entry j is the
+// last run starting at or before DFS index j * 2^B, for j = 0 .. (solid-1) >> B,
+// followed by one more entry, rle_n - 1.  The run holding DFS index i lies
+// between entries i >> B and (i >> B) + 1, inclusive, and there are at most
+// 2 rle_n + 2 entries.
+__host__ __device__ inline uint32_t run_dir_shift(uint32_t rle_n, uint32_t solid) {
+  const int b = __builtin_clz(rle_n) - __builtin_clz(solid);
+  return b > 0 ? (uint32_t)b : 0u;
+}
 
 constexpr uint32_t kPtrBits = 24;
 constexpr uint32_t kPtrMask = (1u << kPtrBits) - 1;
@@ -60,7 +70,7 @@ struct LodData {
   uint32_t level_nodes[16] = {};
   uint16_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   // device image sections, byte offsets inside the blob's image
-  uint64_t off_nodes = 0, off_pre = 0, off_leaves = 0, off_rle_start = 0, off_rle_mat = 0;
+  uint64_t off_nodes = 0, off_pre = 0, off_leaves = 0, off_rle_start = 0, off_rle_dir = 0;
   uint64_t off_begin = 0, off_end = 0;
   uint32_t dev_words = 0;
   uint32_t root_word = 0;

@@ -48,7 +48,7 @@ extern "C" int hk_upload(HkWorld* w, uint32_t ci, const svd_blob* b, int describ
       d.leaves = base + L.off_leaves;
       d.pre = base + L.off_pre;
       d.rle_start = base + L.off_rle_start;
-      d.rle_mat = base + L.off_rle_mat;
+      d.rle_dir = base + L.off_rle_dir;
     }
     d.rle_n = (uint32_t)L.rle_start.size();
     d.root = L.root_word;

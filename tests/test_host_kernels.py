@@ -153,3 +153,43 @@ def test_small_tight_boxes_adversarial(env, cfg):
         ref = ow.trace_frame(lods, gp._oracle_frame(fr), mode=1, threads=NT)
         hits += compare(svdag, raw, ref, label=f"{cfg} frame {i}")
     assert hits > 0
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_material_runs_of_every_length(env, seed):
+    """Material lookup through the run directory: solid chunks whose
+    materials come in runs from one voxel to most of the chunk along the DFS
+    order (so a directory bucket holds zero, one or many run starts), at
+    every LOD; every hit's material equals the oracle's."""
+    svdag, hk = env
+    chunk_log2, grid, lod_count, thr = 5, (2, 1, 1), 3, (20, 40, 0)
+    rng = np.random.default_rng(seed)
+    S = 1 << chunk_log2
+    dense = {}
+    for ci in range(2):
+        g = np.zeros((S, S, S), np.uint8)
+        # boxes of one material of sizes 1..S/2, then single-voxel noise, then holes
+        for _ in range(60):
+            s = int(rng.integers(1, S // 2 + 1))
+            z, y, x = (int(v) for v in rng.integers(0, S - s + 1, 3))
+            g[z:z + s, y:y + s, x:x + s] = int(rng.integers(1, 256))
+        noise = rng.random((S, S, S)) < 0.02
+        g[noise] = rng.integers(1, 256, int(noise.sum()))
+        g[rng.random((S, S, S)) < 0.05] = 0
+        dense[ci] = g
+    blobs = {ci: svdag.svd_chunk_build(g, chunk_log2, lod_count) for ci, g in dense.items()}
+    runs = [svdag.svd_blob_stats_get(blobs[0], k)["n_rle"] for k in range(lod_count)]
+    solid = [svdag.svd_blob_stats_get(blobs[0], k)["n_solid"] for k in range(lod_count)]
+    assert all(r < s for r, s in zip(runs, solid)), "runs longer than a voxel exist"
+    hw = hk.HostWorld(svdag, chunk_log2, grid, lod_count, thr, blobs)
+    ow = oracle.World(chunk_log2, grid, lod_count)
+    for ci, g in dense.items():
+        ow.add_chunk(ci, g)
+    ext = [g * S for g in grid]
+    hits = 0
+    for i, (O, A, BX, BY, W, H) in enumerate(gp._frames(rng, ext, 40, 24, 16)):
+        fr = svdag.make_frame(O, A, BX, BY, W, H)
+        raw, _ = hw.trace(fr, threads=NT)
+        ref = ow.trace_frame(ow.lod_pick(np.array(O, np.int64), thr), gp._oracle_frame(fr), mode=1, threads=NT)
+        hits += compare(svdag, raw, ref, label=f"material runs frame {i}")
+    assert hits > 1000
