@@ -36,6 +36,12 @@
 
 #include "svdag_internal.h"
 
+// Walk events (iter, descend, exit, sibling, pop, chunk_next, chunk_visit,
+// chunk_enter, hit) for a host build that counts them; empty in the library.
+#ifndef SVD_WALK_EVENT
+#define SVD_WALK_EVENT(e) do {} while (0)
+#endif
+
 namespace svd {
 
 struct DescBatch {
@@ -296,6 +302,7 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
   // Chunk walk: c and E describe the current chunk (level CL).
   while (status == kRunning) {
     if (++iter > kMaxIter) { status = kFault; break; }
+    SVD_WALK_EVENT(chunk_visit);
     if (c[0] >= (int32_t)p.grid[0] || c[1] >= (int32_t)p.grid[1] || c[2] >= (int32_t)p.grid[2]) {
       status = kMiss;  // left the world
       break;
@@ -323,6 +330,7 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
         beyond |= r.past_n(a, ((((uint32_t)c[a] << (CL - k)) + b) << (k + 16)) - r.Oml[a]);
       }
       if (!beyond) {
+      SVD_WALK_EVENT(chunk_enter);
       nodes = (gptr32)dag->nodes;
       leaves = (gptr64)dag->leaves;
       const uint32_t root = dag->root;
@@ -344,17 +352,25 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
       // forward on some axis of the mirrored ray and each descent lowers the
       // level, so the walk inside a chunk ends whatever the DAG holds.
       for (;;) {
+        SVD_WALK_EVENT(iter);
         uint32_t full = (mask >> oct) & 1u;
-        if (full && lev == k) { status = kHit; break; }
+        if (full && lev == k) {
+          SVD_WALK_EVENT(hit);
+          status = kHit;
+          break;
+        }
         if (full) {
+          SVD_WALK_EVENT(descend);
           enter_child(lev, k, oct, mask, ptr, lmask, bitmap, nodes, leaves, stk, ss);
           oct = descend(r, c, E, lev);
           full = (mask >> oct) & 1u;
         }
         if (!full) {
+          SVD_WALK_EVENT(exit);
           uint32_t step;
           if (!exit_cell(r, E, step)) { status = kMiss; break; }
           if (((oct ^ r.mm) & step) == 0) {
+            SVD_WALK_EVENT(sibling);
             // the cell was the lower of its pair on every stepped axis: the
             // new cell is its sibling, one cell on along those axes
             _Pragma("unroll") for (int a = 0; a < 3; a++) {
@@ -379,7 +395,11 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
               c[a] >>= (nl - lev);
               E[a] = ((uint32_t)(c[a] + 1) << (nl + 16)) - r.Oml[a];
             }
-            if (pl > CL) break;  // into the next chunk (level CL)
+            if (pl > CL) {  // into the next chunk (level CL)
+              SVD_WALK_EVENT(chunk_next);
+              break;
+            }
+            SVD_WALK_EVENT(pop);
             lev = nl;
             oct = (((uint32_t)c[0] & 1u) | (((uint32_t)c[1] & 1u) << 1) | (((uint32_t)c[2] & 1u) << 2)) ^ r.mm;
             if (pl >= k + 3) {

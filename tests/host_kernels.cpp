@@ -3,6 +3,19 @@
 // images, so CPU-only test runs check it against the oracle; likewise the GPU
 // scene generator's per-element code, checked against the host generator.  Not part of
 // libsvdag; nothing here touches a GPU.
+#include <cstdint>
+
+// Walk events of trace_pixel, counted per host thread (see hk_trace_counts).
+struct WalkCounts {
+  uint64_t iter, descend, exit, sibling, pop, chunk_next, chunk_visit, chunk_enter, hit;
+};
+static thread_local WalkCounts g_walk;
+#ifdef __HIP_DEVICE_COMPILE__
+#define SVD_WALK_EVENT(e) do {} while (0)  // the device pass of this host-only file counts nothing
+#else
+#define SVD_WALK_EVENT(e) (g_walk.e++)
+#endif
+
 #include "kernels.hip"
 #include "../paper_2505_02017_amd/scenes/scenegen_gpu.hip"
 
@@ -63,9 +76,25 @@ extern "C" int hk_upload(HkWorld* w, uint32_t ci, const svd_blob* b, int describ
 
 // Stage, optional beam pass (16x4 tiles, as the per-view launch) and trace
 // of every pixel; records in `out` (width*height x 16 bytes), the view table
-// in `view_out` (may be NULL).
+// in `view_out` (may be NULL).  With `counts` (may be NULL), the walk events
+// summed over all pixels, in WalkCounts order, then per 64-pixel tile the
+// largest count of inner-loop iterations of one pixel, summed over tiles, and
+// the number of tiles.
+static int trace_impl(HkWorld* w, const svd_ray_frame* f, uint32_t flags, svd_hit* out, uint32_t* view_out,
+                      uint32_t threads, uint64_t* counts);
+
 extern "C" int hk_trace(HkWorld* w, const svd_ray_frame* f, uint32_t flags, svd_hit* out, uint32_t* view_out,
                         uint32_t threads) {
+  return trace_impl(w, f, flags, out, view_out, threads, nullptr);
+}
+
+extern "C" int hk_trace_counts(HkWorld* w, const svd_ray_frame* f, uint32_t flags, svd_hit* out, uint32_t threads,
+                               uint64_t* counts) {
+  return trace_impl(w, f, flags, out, nullptr, threads, counts);
+}
+
+static int trace_impl(HkWorld* w, const svd_ray_frame* f, uint32_t flags, svd_hit* out, uint32_t* view_out,
+                      uint32_t threads, uint64_t* counts) {
   StageParams sp;
   memset(&sp, 0, sizeof(sp));
   memcpy(sp.O, f->O, sizeof(sp.O));
@@ -110,9 +139,14 @@ extern "C" int hk_trace(HkWorld* w, const svd_ray_frame* f, uint32_t flags, svd_
   tp.desc = w->tab.data();
 
   const uint32_t nt = std::max(1u, std::min(threads, 64u));
+  constexpr int kEvents = sizeof(WalkCounts) / sizeof(uint64_t);
+  std::vector<uint64_t> part((size_t)nt * (kEvents + 2), 0);
   auto run_rows = [&](uint32_t t0) {
+    g_walk = WalkCounts{};
+    uint64_t* mine = &part[(size_t)t0 * (kEvents + 2)];
     for (uint32_t ty = t0; ty < tiles_y; ty += nt) {
       for (uint32_t tx = 0; tx < tiles_x; tx++) {
+        uint64_t tile_max = 0;
         uint32_t s = 0;
         if (flags & SVD_BEAM) {
           uint32_t bstk[2 * 8];
@@ -123,19 +157,30 @@ extern "C" int hk_trace(HkWorld* w, const svd_ray_frame* f, uint32_t flags, svd_
         for (uint32_t py = ty * th; py < std::min((ty + 1) * th, H); py++)
           for (uint32_t px = tx * tw; px < std::min((tx + 1) * tw, W); px++) {
             uint32_t stk[8];
+            const uint64_t it0 = g_walk.iter;
             const uint4 r = trace_pixel(tp, px, py, stk, 1, s);
+            tile_max = std::max<uint64_t>(tile_max, g_walk.iter - it0);
             svd_hit& h = out[(size_t)py * W + px];
             h.xy = r.x;
             h.zf = r.y;
             memcpy(&h.t, &r.z, 4);
             h.chunk = r.w;
           }
+        mine[kEvents] += tile_max;
+        mine[kEvents + 1] += 1;
       }
     }
+    memcpy(mine, &g_walk, sizeof(WalkCounts));
   };
   std::vector<std::thread> pool;
   for (uint32_t t = 0; t < nt; t++) pool.emplace_back(run_rows, t);
   for (auto& t : pool) t.join();
+  if (counts) {
+    for (int e = 0; e < kEvents + 2; e++) {
+      counts[e] = 0;
+      for (uint32_t t = 0; t < nt; t++) counts[e] += part[(size_t)t * (kEvents + 2) + e];
+    }
+  }
   return SVD_OK;
 }
 

@@ -48,6 +48,7 @@ def lib():
         L.hk_world_free.restype = None
         L.hk_upload.argtypes = [vp, u32, vp, ctypes.c_int]
         L.hk_trace.argtypes = [vp, vp, u32, vp, vp, u32]
+        L.hk_trace_counts.argtypes = [vp, vp, u32, vp, u32, vp]
         L.hk_beam_cube.argtypes = [vp, vp, vp, vp, u32, u32, u32, u32, vp, ctypes.c_int32, vp]
         L.hk_beam_cube.restype = ctypes.c_int
         L.hk_scene_chunk.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
@@ -80,6 +81,20 @@ class HostWorld:
         view = np.zeros(self.n, np.uint32)
         assert lib().hk_trace(self.w, ctypes.byref(frame), flags, out.ctypes.data, view.ctypes.data, threads) == 0
         return out, view
+
+
+WALK_EVENTS = ("iter", "descend", "exit", "sibling", "pop", "chunk_next", "chunk_visit", "chunk_enter", "hit",
+               "tile_max_iter", "tiles")
+
+
+def trace_counts(world, frame, flags=0, threads=8):
+    """Records and walk-event counts of a host trace of `frame` (see
+    hk_trace_counts): a dict over WALK_EVENTS."""
+    out = np.zeros((frame.width * frame.height, 4), np.uint32)
+    cnt = np.zeros(len(WALK_EVENTS), np.uint64)
+    assert lib().hk_trace_counts(world.w, ctypes.byref(frame), flags, out.ctypes.data, threads,
+                                 cnt.ctypes.data) == 0
+    return out, dict(zip(WALK_EVENTS, (int(v) for v in cnt)))
 
 
 def beam_cube(O, A, BX, BY, tile, lo, s):

@@ -193,3 +193,29 @@ def test_material_runs_of_every_length(env, seed):
         ref = ow.trace_frame(ow.lod_pick(np.array(O, np.int64), thr), gp._oracle_frame(fr), mode=1, threads=NT)
         hits += compare(svdag, raw, ref, label=f"material runs frame {i}")
     assert hits > 1000
+
+
+def test_walk_event_counts_are_consistent(env):
+    """The host build's walk-event counts (the per-step evidence behind the
+    trace's instruction budget) add up: every exit is a sibling step, a pop
+    to an ancestor or a move to the next chunk; every hit record is one hit
+    event; every loop iteration ends in a hit, an exit, or a descent into a
+    non-empty cell."""
+    svdag, hk = env
+    sw = scenes.SceneWorld("custom", 23, chunk_log2=6, grid=(4, 4, 2))
+    dense = {ci: sw.chunk(c) for ci, c in enumerate(sw.chunks())}
+    thr = (48, 96, 160)
+    blobs = {ci: svdag.svd_chunk_build(g, 6, 4) for ci, g in dense.items()}
+    hw = hk.HostWorld(svdag, 6, sw.grid, 4, thr, blobs)
+    for i, cam in enumerate(sw.views(3, 9, 96, 64)):
+        fr = svdag.svd_camera_frame(svdag.to_camera(cam))
+        raw, c = hk.trace_counts(hw, fr, threads=NT)
+        raw2, _ = hw.trace(fr, threads=NT)
+        assert np.array_equal(raw, raw2)
+        hits = int((svdag.decode_hits(raw)["hit"] == 1).sum())
+        assert c["hit"] == hits > 0
+        assert c["exit"] == c["sibling"] + c["pop"] + c["chunk_next"]
+        assert c["hit"] + c["exit"] <= c["iter"] <= c["hit"] + c["exit"] + c["descend"]
+        assert c["chunk_enter"] <= c["chunk_visit"]
+        assert c["tiles"] == ((96 + 15) // 16) * ((64 + 3) // 4)
+        assert c["iter"] / (96 * 64) <= c["tile_max_iter"] / c["tiles"]
