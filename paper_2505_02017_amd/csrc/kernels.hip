@@ -354,9 +354,12 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
       for (;;) {
         SVD_WALK_EVENT(iter);
         uint32_t full = (mask >> oct) & 1u;
-        if (full && lev == k) {
+        // A non-empty cell at the LOD's level (the walk never goes below
+        // level k, so lev <= k means lev == k) is the hit.  The loop leaves
+        // without setting the status: the hit is the one exit with the
+        // current cell non-empty, read after the loop.
+        if (full && lev <= k) {
           SVD_WALK_EVENT(hit);
-          status = kHit;
           break;
         }
         if (full) {
@@ -416,6 +419,7 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
           }
         }
       }
+      if (status == kRunning && ((mask >> oct) & 1u)) status = kHit;
       continue;
       }
     }
