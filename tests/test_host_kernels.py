@@ -219,3 +219,38 @@ def test_walk_event_counts_are_consistent(env):
         assert c["chunk_enter"] <= c["chunk_visit"]
         assert c["tiles"] == ((96 + 15) // 16) * ((64 + 3) // 4)
         assert c["iter"] / (96 * 64) <= c["tile_max_iter"] / c["tiles"]
+
+
+def test_zero_direction_rays(env):
+    """Pixels whose direction is exactly zero never move: a hit at the
+    origin's cell when it is solid at the picked LOD, else a miss; on the
+    oracle the same."""
+    svdag, hk = env
+    chunk_log2, grid, lod_count, thr = 4, (2, 2, 1), 2, (20, 0, 0)
+    rng = np.random.default_rng(77)
+    S = 1 << chunk_log2
+    dense = {ci: scenes.random_grid(rng, S, 0.5) for ci in range(4)}
+    blobs = {ci: svdag.svd_chunk_build(g, chunk_log2, lod_count) for ci, g in dense.items()}
+    hw = hk.HostWorld(svdag, chunk_log2, grid, lod_count, thr, blobs)
+    ow = oracle.World(chunk_log2, grid, lod_count)
+    for ci, g in dense.items():
+        ow.add_chunk(ci, g)
+    F = 1 << 16
+    hits = misses = 0
+    for i in range(90):
+        # pixel (0, 0) has D = A = 0; the rest of the row points along +-x.
+        # A third of the origins lie in the world's low corner, where cell
+        # and chunk coordinates coincide (so a walk that went on from such a
+        # cell would not leave the world by accident).
+        hi = [2, 2, 2] if i % 3 == 0 else [2 * S, 2 * S, S]
+        O = [int(rng.integers(-F if i % 3 else 0, hi[a] * F + (F if i % 3 else 0))) for a in range(3)]
+        O = [min(max(o, -F), (2 * S + 1) * F) for o in O]
+        sx = 1 if i % 2 else -1
+        fr = svdag.make_frame(O, [0, 0, 0], [sx * 977, 31, -17], [0, 0, 0], 5, 1)
+        raw, _ = hw.trace(fr, threads=1)
+        ref = ow.trace_frame(ow.lod_pick(np.array(O, np.int64), thr), gp._oracle_frame(fr), mode=1, threads=1)
+        compare(svdag, raw, ref, label=f"zero-direction frame {i}")
+        h = svdag.decode_hits(raw[:1])["hit"][0]
+        hits += int(h == 1)
+        misses += int(h == 0)
+    assert hits > 5 and misses > 5
