@@ -371,7 +371,7 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
         if (!full) {
           SVD_WALK_EVENT(exit);
           uint32_t step;
-          if (!exit_cell(r, E, step)) { status = kMiss; break; }
+          if (!exit_cell(r, E, step)) break;  // D == 0: the ray never leaves the cell
           if (((oct ^ r.mm) & step) == 0) {
             SVD_WALK_EVENT(sibling);
             // the cell was the lower of its pair on every stepped axis: the
@@ -419,7 +419,10 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
           }
         }
       }
-      if (status == kRunning && ((mask >> oct) & 1u)) status = kHit;
+      // the loop's exits: a hit (the current cell non-empty), the next chunk,
+      // or a ray that never moves (D == 0) in an empty cell: a miss
+      if ((mask >> oct) & 1u) status = kHit;
+      else if ((r.ad2[0] | r.ad2[1] | r.ad2[2]) == 0) status = kMiss;
       continue;
       }
     }
