@@ -238,7 +238,8 @@ int svd_trace_frame(svd_world* w, const svd_ray_frame* frame, svd_hit* out_dev, 
  *   Errors as svd_trace_frame.  flags: SVD_NO_CULL, SVD_BEAM.
  * svd_view_beam (optional): the beam pass (ESVO's beam optimisation, Section
  *   2.2: a coarse distance pass that moves the rays' starting points; here
- *   made exact, so records do not change): per 16x4-pixel tile, a
+ *   made exact, so records do not change): per wave tile (the world's
+ *   tiling, svd_world_set_tiling), a
  *   distance within which no ray of the tile can meet a cell it could hit,
  *   parked in the tile's first record of out_dev.  The next svd_view_trace
  *   into the same out_dev then starts each ray there instead of running the
@@ -248,8 +249,8 @@ int svd_trace_frame(svd_world* w, const svd_ray_frame* frame, svd_hit* out_dev, 
  *   been given an identical frame (else SVD_EINVAL); with SVD_BEAM staged,
  *   runs the beam pass first unless svd_view_beam did.
  * The beam pass is off by default: on MI355X it cuts the trace's time by
- * about a quarter, but its own search (one serial chain of dependent loads
- * per tile) costs more than that. */
+ * about a fifth, but its own search (one serial chain of dependent loads
+ * per tile) costs about twice the trace. */
 int svd_view_stage(svd_world* w, const svd_ray_frame* frame, uint32_t flags, void* stream);
 int svd_view_beam(svd_world* w, const svd_ray_frame* frame, svd_hit* out_dev, void* stream);
 int svd_view_trace(svd_world* w, const svd_ray_frame* frame, svd_hit* out_dev, void* stream);

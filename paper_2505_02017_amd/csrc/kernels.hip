@@ -125,7 +125,7 @@ int launch_chunk_stage(const StageParams& p, void* stream) {
 }
 
 // ------------------------------------------------------------------- trace
-constexpr int kBlock = 256;      // 4 waves; each wave is one 8x8 pixel tile
+constexpr int kBlock = 256;      // 4 waves; each wave traces one 64-pixel tile at a time
 constexpr int kStackLevels = 8;  // node levels 3..10
 constexpr uint32_t kMaxIter = 1u << 22;
 constexpr uint32_t kFaultChunk = 0xFFFFFFFEu;

@@ -95,7 +95,7 @@ class svd_tune_result(ctypes.Structure):
                 ("key", ctypes.c_char * 384)]
 
     def as_dict(self) -> dict:
-        return {"tile": f"{self.tile_w}x{64 // self.tile_w}", "claim": self.claim,
+        return {"tile": f"{self.tile_w}x{64 // self.tile_w}", "tile_w": self.tile_w, "claim": self.claim,
                 "blocks_per_cu": self.blocks_per_cu, "from_cache": bool(self.from_cache),
                 "ms": round(float(self.ms), 4), "configs_timed": self.configs_timed,
                 "key": self.key.decode()}
