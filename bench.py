@@ -65,11 +65,29 @@ def default_tune_cache():
 
 
 def tune_cache_path(args):
-    """The tuning cache file (its directory created), or None."""
+    """The tuning cache file (its directory created), or None (no cache, or
+    a directory that cannot be created)."""
     if not args.tune_cache or args.tune_cache == "none":
         return None
-    os.makedirs(os.path.dirname(os.path.abspath(args.tune_cache)), exist_ok=True)
+    try:
+        os.makedirs(os.path.dirname(os.path.abspath(args.tune_cache)), exist_ok=True)
+    except OSError as e:
+        log(f"tuning cache disabled: {e}")
+        return None
     return args.tune_cache
+
+
+def tune_world(svdag, world, frames, out, flags, cache, stream):
+    """svd_world_tune through the cache; a cache that cannot be written
+    leaves the tuned choice applied (the library's contract) and is
+    reported, not fatal."""
+    try:
+        return svdag.svd_world_tune(world, frames, out, flags, reps=3, cache_path=cache, stream=stream), cache
+    except svdag.SvdError as e:
+        if e.code != svdag.SVD_EIO:
+            raise
+        log(f"tuning cache not written ({e}); tuning without it")
+        return svdag.svd_world_tune(world, frames, out, flags, reps=3, cache_path=None, stream=stream), None
 
 
 def counter_profile(workload):
@@ -346,7 +364,7 @@ def main():
                        "from_cache": False, "fixed": True}
         log(f"per-view tile {args.view_tile}x{64 // args.view_tile}, {args.view_occupancy} blocks/CU (fixed)")
     else:
-        tuned = svdag.svd_world_tune(world, frames_gpu, out, stage_flags, reps=3, cache_path=cache, stream=stream)
+        tuned, cache = tune_world(svdag, world, frames_gpu, out, stage_flags, cache, stream)
         view_tuning = tuned.as_dict()
         log(f"per-view tile {tuned.tile_w}x{64 // tuned.tile_w}, {tuned.blocks_per_cu} blocks/CU "
             + ("(from the tuning cache)" if tuned.from_cache else f"(tuned: {tuned.configs_timed} configurations)"))
@@ -605,7 +623,13 @@ def bench_batched(args, sw, world, svdag, torch, cache):
     out_p = torch.empty((nrec, 4), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
     batch = svdag.svd_batch_create(world, len(cams))
-    tuned = svdag.svd_batch_tune_cached(batch, cams, out_b, reps=3, cache_path=cache, stream=stream)
+    try:
+        tuned = svdag.svd_batch_tune_cached(batch, cams, out_b, reps=3, cache_path=cache, stream=stream)
+    except svdag.SvdError as e:
+        if e.code != svdag.SVD_EIO:
+            raise
+        log(f"tuning cache not written ({e}); tuning without it")
+        tuned = svdag.svd_batch_tune_cached(batch, cams, out_b, reps=3, cache_path=None, stream=stream)
     tw, claim, occ = tuned.tile_w, tuned.claim, tuned.blocks_per_cu
     log(f"batch of {len(cams)} views ({nrec} rays): tile {tw}x{64 // tw}, claim {claim}, {occ} blocks/CU "
         + ("(from the tuning cache)" if tuned.from_cache else f"(tuned: {tuned.configs_timed} configurations)"))

@@ -70,3 +70,16 @@ def test_host_cores_reports_the_usable_cpus():
     assert nproc == len(os.sched_getaffinity(0))
     if limit is None:
         assert cores == nproc
+
+
+def test_tune_cache_path(tmp_path):
+    """The bench's tuning cache: its directory is created; 'none' turns it
+    off; a directory that cannot be created turns it off instead of failing
+    the run."""
+    import types
+    import bench
+    p = tmp_path / "a" / "b" / "tune.txt"
+    assert bench.tune_cache_path(types.SimpleNamespace(tune_cache=str(p))) == str(p)
+    assert p.parent.is_dir()
+    assert bench.tune_cache_path(types.SimpleNamespace(tune_cache="none")) is None
+    assert bench.tune_cache_path(types.SimpleNamespace(tune_cache="/proc/no-such-dir/tune.txt")) is None
