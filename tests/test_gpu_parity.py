@@ -238,3 +238,46 @@ def test_errors_before_enqueue(env):
         with pytest.raises(svdag.SvdError) as e:
             svdag.svd_trace_view(w, svdag.to_camera(bad), out)
         assert e.value.code == code
+
+
+def test_zero_direction_rays(env):
+    """Pixels whose direction is exactly zero never move: a hit at the
+    origin's cell when it is solid at the picked LOD, else a miss; equal to
+    the oracle on the GPU too (per-view and batched)."""
+    svdag, torch = env
+    chunk_log2, grid, lod_count, thr = 4, (2, 2, 1), 2, (20, 0, 0)
+    rng = np.random.default_rng(77)
+    S = 1 << chunk_log2
+    dense = {ci: scenes.random_grid(rng, S, 0.5) for ci in range(4)}
+    w = gpu_world(svdag, torch, chunk_log2, grid, lod_count, build_blobs(svdag, chunk_log2, lod_count, dense), thr,
+                  extra_bytes=1 << 20)
+    ow = oracle_world(chunk_log2, grid, lod_count, dense)
+    hits = misses = 0
+    frames = []
+    for i in range(90):
+        # pixel (0, 0) has D = A = 0; a third of the origins lie in the
+        # world's low corner, where cell and chunk coordinates coincide
+        hi = [2, 2, 2] if i % 3 == 0 else [2 * S, 2 * S, S]
+        O = [int(rng.integers(-F if i % 3 else 0, hi[a] * F + (F if i % 3 else 0))) for a in range(3)]
+        O = [min(max(o, -F), (2 * S + 1) * F) for o in O]
+        sx = 1 if i % 2 else -1
+        fr = svdag.make_frame(O, [0, 0, 0], [sx * 977, 31, -17], [0, 0, 0], 5, 1)
+        frames.append(fr)
+        raw = trace_gpu(svdag, torch, w, fr)
+        ref = ow.trace_frame(ow.lod_pick(np.array(O, np.int64), thr), _oracle_frame(fr), mode=1, threads=NT)
+        compare(svdag, raw, ref, label=f"zero-direction frame {i}")
+        h = svdag.decode_hits(raw[:1])["hit"][0]
+        hits += int(h == 1)
+        misses += int(h == 0)
+    assert hits > 5 and misses > 5
+    # the same frames as one batch
+    out = torch.empty((5 * len(frames), 4), dtype=torch.int32, device="cuda")
+    b = svdag.svd_batch_create(w, len(frames))
+    svdag.svd_batch_trace_frames(b, frames, out)
+    torch.cuda.synchronize()
+    raw_b = out.cpu().numpy()
+    for i, fr in enumerate(frames):
+        ref = ow.trace_frame(ow.lod_pick(np.array(list(fr.O), np.int64), thr), _oracle_frame(fr), mode=1,
+                             threads=NT)
+        compare(svdag, raw_b[5 * i:5 * i + 5], ref, label=f"zero-direction batch view {i}")
+    svdag.svd_batch_destroy(b)
