@@ -513,21 +513,53 @@ __device__ __forceinline__ bool take_tiles(uint32_t* queue, uint32_t total, uint
   return false;
 }
 
+// Tiles of queue q in the per-view trace: the tile rows y with y % kQueues
+// == q, each left to right, rows top to bottom.  Interleaving the rows
+// spreads every part of the image (the costly rows around a horizon, the
+// cheap sky) over all the queues, so that they run dry together and each
+// ends on the image's last rows, instead of one queue's band of costly
+// rows finishing alone.
+__host__ __device__ __forceinline__ uint32_t row_queue_tiles(uint32_t q, uint32_t tiles_x, uint32_t tiles_y) {
+  return q < tiles_y ? ((tiles_y - 1 - q) / kQueues + 1) * tiles_x : 0u;
+}
+__host__ __device__ __forceinline__ uint32_t row_queue_tile(uint32_t q, uint32_t j, uint32_t tiles_x) {
+  return (q + kQueues * (j / tiles_x)) * tiles_x + j % tiles_x;
+}
+
+// Next tile of the wave from its home queue (row-interleaved), or from the
+// following queues once that one is dry; false when all are.
+__device__ __forceinline__ bool take_row_tile(uint32_t* queue, uint32_t tiles_x, uint32_t tiles_y, uint32_t home,
+                                              uint32_t lane, uint32_t& qi, uint32_t& t) {
+  for (; qi < kQueues; qi++) {
+    const uint32_t q = (home + qi) % kQueues;
+    uint32_t j = 0;
+    if (lane == 0) j = atomicAdd(&queue[q * kQueueStride], 1u);
+    j = __builtin_amdgcn_readlane(j, 0);  // wave-uniform: the tile math stays scalar
+    if (j < row_queue_tiles(q, tiles_x, tiles_y)) {
+      t = row_queue_tile(q, j, tiles_x);
+      return true;
+    }
+  }
+  return false;
+}
+
 // Held to 6 waves per SIMD (80 VGPRs at most; it fits in fewer).
 // Persistent: a machine-filling grid whose waves each take 64-pixel tiles
-// (tile_w x 64/tile_w) from the per-XCD queues until the image is done, so that no wave idles
-// while the slower waves of its work-group finish (ray costs vary widely per
-// tile).  Waves that find every queue dry count themselves out; the last one
-// clears the queues, so every launch starts from zero.
+// (tile_w x 64/tile_w) from the per-XCD, row-interleaved queues until the
+// image is done, so that no wave idles while the slower waves of its
+// work-group finish (ray costs vary widely per tile).  Waves that find every
+// queue dry count themselves out; the last one clears the queues, so every
+// launch starts from zero.
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 6))) void trace_kernel(TraceParams p) {
   __shared__ uint32_t stk[kStackLevels][kBlock];
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t tw = p.tile_w, tw_log2 = __builtin_ctz(p.tile_w), th = 64u >> tw_log2;
   const uint32_t home = blockIdx.x % kQueues;
+  const uint32_t tiles_y = p.total_tiles / p.tiles_x;
   uint32_t qi = 0;
   for (;;) {
-    uint32_t t = 0, t_end = 0;
-    if (!take_tiles(p.queue, p.total_tiles, 1u, home, lane, qi, t, t_end)) {
+    uint32_t t = 0;
+    if (!take_row_tile(p.queue, p.tiles_x, tiles_y, home, lane, qi, t)) {
       if (lane == 0 && atomicAdd(&p.queue[kQueues * kQueueStride], 1u) == gridDim.x * (kBlock / 64) - 1) {
         for (uint32_t i = 0; i <= kQueues; i++) atomicExch(&p.queue[i * kQueueStride], 0u);
       }

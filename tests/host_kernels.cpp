@@ -184,6 +184,16 @@ static int trace_impl(HkWorld* w, const svd_ray_frame* f, uint32_t flags, svd_hi
   return SVD_OK;
 }
 
+// The per-view trace's row-interleaved tile queues: every tile of queue 0,
+// then of queue 1, ... into `out` (room for tiles_x * tiles_y); returns the
+// count.
+extern "C" uint32_t hk_row_queue_tiles(uint32_t tiles_x, uint32_t tiles_y, uint32_t* out) {
+  uint32_t n = 0;
+  for (uint32_t q = 0; q < kQueues; q++)
+    for (uint32_t j = 0; j < row_queue_tiles(q, tiles_x, tiles_y); j++) out[n++] = row_queue_tile(q, j, tiles_x);
+  return n;
+}
+
 // The beam pass's cone test and distance for one tile and one cube, as the
 // kernels evaluate them: returns -1 for a degenerate cone, else 1 when the
 // cube [lo, lo + s] is dropped as outside the cone; *dist gets the cube's

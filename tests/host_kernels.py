@@ -49,6 +49,8 @@ def lib():
         L.hk_upload.argtypes = [vp, u32, vp, ctypes.c_int]
         L.hk_trace.argtypes = [vp, vp, u32, vp, vp, u32]
         L.hk_trace_counts.argtypes = [vp, vp, u32, vp, u32, vp]
+        L.hk_row_queue_tiles.argtypes = [u32, u32, vp]
+        L.hk_row_queue_tiles.restype = u32
         L.hk_beam_cube.argtypes = [vp, vp, vp, vp, u32, u32, u32, u32, vp, ctypes.c_int32, vp]
         L.hk_beam_cube.restype = ctypes.c_int
         L.hk_scene_chunk.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
@@ -95,6 +97,13 @@ def trace_counts(world, frame, flags=0, threads=8):
     assert lib().hk_trace_counts(world.w, ctypes.byref(frame), flags, out.ctypes.data, threads,
                                  cnt.ctypes.data) == 0
     return out, dict(zip(WALK_EVENTS, (int(v) for v in cnt)))
+
+
+def row_queue_tiles(tiles_x, tiles_y):
+    """The per-view trace's tile queues, queue 0 first (see hk_row_queue_tiles)."""
+    out = np.full(tiles_x * tiles_y + 64, 0xFFFFFFFF, np.uint32)
+    n = lib().hk_row_queue_tiles(tiles_x, tiles_y, out.ctypes.data)
+    return out[:n], out[n:]
 
 
 def beam_cube(O, A, BX, BY, tile, lo, s):

@@ -254,3 +254,21 @@ def test_zero_direction_rays(env):
         hits += int(h == 1)
         misses += int(h == 0)
     assert hits > 5 and misses > 5
+
+
+@pytest.mark.parametrize("tiles_x,tiles_y", [(1, 1), (1, 7), (5, 1), (3, 8), (3, 9), (7, 15), (160, 360),
+                                             (240, 180), (4, 17), (2, 65)])
+def test_row_queue_tiles_cover_every_tile_once(env, tiles_x, tiles_y):
+    """The per-view trace's queues hand out every tile of the image exactly
+    once (queue q: the tile rows y with y % 8 == q, each left to right)."""
+    svdag, hk = env
+    tiles, spare = hk.row_queue_tiles(tiles_x, tiles_y)
+    assert np.array_equal(np.sort(tiles), np.arange(tiles_x * tiles_y))
+    assert np.all(spare == 0xFFFFFFFF)
+    # queue order: each queue's rows in increasing order, every 8th row
+    pos, q_rows = 0, []
+    for q in range(8):
+        n = len(range(q, tiles_y, 8)) * tiles_x
+        q_rows.append(tiles[pos:pos + n] // tiles_x)
+        pos += n
+        assert np.all(q_rows[-1] % 8 == q) and np.all(np.diff(q_rows[-1]) >= 0)
