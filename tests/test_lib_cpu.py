@@ -244,3 +244,50 @@ def test_tune_cache_file(tmp_path):
         svdag.svd_tune_cache_store(str(tmp_path / "no" / "tune.txt"), k1, 16, 1, 6)
     assert e.value.code == svdag.SVD_EIO
     assert not [p for p in os.listdir(tmp_path) if ".tmp." in p]
+
+
+def test_plain_c_caller(tmp_path):
+    """The boundary is a C ABI: a C99 program (pedantic, warnings as errors)
+    includes svdag.h, links libsvdag.so and uses entry points that need no
+    GPU (the kernel hash, the tuning cache, the camera frame, an error
+    message)."""
+    import shutil
+    import subprocess
+    svdag = _svdag()
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    src = tmp_path / "caller.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <string.h>
+#include "svdag.h"
+int main(int argc, char** argv) {
+  (void)argc;
+  svd_tune_result r;
+  memset(&r, 0, sizeof(r));
+  strcpy(r.key, "dev=test kind=view");
+  r.tile_w = 8; r.claim = 1; r.blocks_per_cu = 5; r.ms = 0.25f;
+  if (svd_tune_cache_store(argv[1], &r) != SVD_OK) return 1;
+  svd_tune_result back;
+  if (svd_tune_cache_lookup(argv[1], "dev=test kind=view", &back) != SVD_OK) return 2;
+  if (back.tile_w != 8 || back.blocks_per_cu != 5 || !back.from_cache) return 3;
+  if (svd_tune_cache_lookup(argv[1], "dev=other", &back) != SVD_ENOTFOUND) return 4;
+  svd_camera cam = {{100.0f, 100.0f, 50.0f}, {200.0f, 150.0f, 20.0f}, {0.0f, 0.0f, 1.0f}, 60.0f, 64, 32};
+  svd_ray_frame f;
+  if (svd_camera_frame(&cam, &f) != SVD_OK || f.width != 64) return 5;
+  cam.vfov_deg = 0.0f;
+  if (svd_camera_frame(&cam, &f) == SVD_OK || strlen(svd_last_error()) == 0) return 6;
+  printf("%s\n", svd_kernel_hash());
+  return 0;
+}
+''')
+    exe = tmp_path / "caller"
+    libdir = os.path.dirname(svdag.LIB_PATH)
+    r = subprocess.run(["gcc", "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror", f"-I{ROOT}/include",
+                        str(src), "-o", str(exe), f"-L{libdir}", "-lsvdag", f"-Wl,-rpath,{libdir}"],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe), str(tmp_path / "tune.txt")], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, (r.returncode, r.stderr)
+    from paper_2505_02017_amd import build
+    assert r.stdout.strip() == build.kernel_source_hash()
