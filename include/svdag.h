@@ -255,6 +255,29 @@ int svd_view_stage(svd_world* w, const svd_ray_frame* frame, uint32_t flags, voi
 int svd_view_beam(svd_world* w, const svd_ray_frame* frame, svd_hit* out_dev, void* stream);
 int svd_view_trace(svd_world* w, const svd_ray_frame* frame, svd_hit* out_dev, void* stream);
 
+/* Kernel time of trace passes, for measurement (the duration of the
+ * per-pixel trace kernel of Section 3.5 ray marching, with the beam kernel
+ * when the pass runs one).
+ * svd_world_time_traces: arms the world to time its next n trace passes
+ *   (svd_view_trace, svd_trace_frame, svd_trace_view; batches and served
+ *   requests are not timed).  A pass's start and stop timestamps come from
+ *   the dispatch packets of its first and last kernel, so no marker command
+ *   is put on the stream and back-to-back launches keep their spacing
+ *   (event markers between kernels each add a few microseconds of idle
+ *   time).  Passes after the n-th run untimed.  n = 0 disarms; arming again
+ *   drops earlier records.  Both calls wait for passes already recorded.
+ *   Errors: SVD_EINVAL for n > SVD_MAX_TIMED_PASSES (nothing changes),
+ *   SVD_EDEVICE if the events cannot be created (the world is then
+ *   disarmed).
+ * svd_world_trace_times: waits for the recorded passes and writes the
+ *   durations of the first min(n, recorded) of them, in milliseconds and in
+ *   launch order, to host array ms; *count gets how many were written.
+ *   Errors: SVD_EINVAL for null arguments, SVD_EDEVICE if a pass failed
+ *   (*count then holds the durations written before it). */
+#define SVD_MAX_TIMED_PASSES 65536u
+int svd_world_time_traces(svd_world* w, uint32_t n);
+int svd_world_trace_times(svd_world* w, float* ms, uint32_t n, uint32_t* count);
+
 /* Occupancy of the per-view persistent trace: the grid is blocks_per_cu x
  * (compute units) blocks of 4 waves, but never more waves than the view has
  * 64-pixel tiles.  0 selects the default, 6 blocks per CU (or the most that

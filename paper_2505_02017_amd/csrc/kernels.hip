@@ -29,6 +29,7 @@
 // coordinates without plane tests.  The node words of the current path live
 // in LDS.  Hits are resolved after the loop (DFS index, material run through
 // the run directory, t, face).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -581,8 +582,12 @@ int trace_occupancy(uint32_t* blocks_per_cu) {
   return SVD_OK;
 }
 
-int launch_trace(const TraceParams& p, uint32_t blocks, void* stream) {
-  hipLaunchKernelGGL(trace_kernel, dim3(blocks), dim3(kBlock), 0, (hipStream_t)stream, p);
+int launch_trace(const TraceParams& p, uint32_t blocks, void* stream, void* start, void* stop) {
+  if (start || stop)
+    hipExtLaunchKernelGGL(trace_kernel, dim3(blocks), dim3(kBlock), 0, (hipStream_t)stream, (hipEvent_t)start,
+                          (hipEvent_t)stop, 0, p);
+  else
+    hipLaunchKernelGGL(trace_kernel, dim3(blocks), dim3(kBlock), 0, (hipStream_t)stream, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return svd_fail(SVD_EDEVICE, "trace launch: %s", hipGetErrorString(e));
   return SVD_OK;
@@ -824,9 +829,13 @@ __global__ __launch_bounds__(kBeamBlock) void beam_kernel(BeamParams p) {
   reinterpret_cast<uint32_t*>(p.out)[((size_t)y0 * p.W + x0) * 4] = d;
 }
 
-int launch_beam(const BeamParams& p, void* stream) {
+int launch_beam(const BeamParams& p, void* stream, void* start) {
   const uint32_t blocks = (p.total_tiles + kBeamBlock - 1) / kBeamBlock;
-  hipLaunchKernelGGL(beam_kernel, dim3(blocks), dim3(kBeamBlock), 0, (hipStream_t)stream, p);
+  if (start)
+    hipExtLaunchKernelGGL(beam_kernel, dim3(blocks), dim3(kBeamBlock), 0, (hipStream_t)stream, (hipEvent_t)start,
+                          nullptr, 0, p);
+  else
+    hipLaunchKernelGGL(beam_kernel, dim3(blocks), dim3(kBeamBlock), 0, (hipStream_t)stream, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return svd_fail(SVD_EDEVICE, "beam launch: %s", hipGetErrorString(e));
   return SVD_OK;

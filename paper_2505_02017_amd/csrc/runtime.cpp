@@ -478,6 +478,7 @@ extern "C" int svd_view_stage(svd_world* w, const svd_ray_frame* f, uint32_t fla
   w->has_staged = true;
   w->staged_beam = (flags & SVD_BEAM) != 0;
   w->beamed = nullptr;
+  w->timing_started = false;
   return SVD_OK;
 }
 
@@ -487,8 +488,11 @@ extern "C" int svd_view_beam(svd_world* w, const svd_ray_frame* f, svd_hit* out_
     return svd_fail(SVD_EINVAL, "beam: the frame was not staged by the last svd_view_stage");
   if (w->absent) return svd_fail(SVD_ENOTFOUND, "beam: %u (chunk, LOD) slots were never uploaded", w->absent);
   if (!w->staged_beam) return SVD_OK;
-  const int rc = launch_beam(view_beam_params(w, f, w->d_view, out_dev), stream);
+  // an armed pass starts at its beam launch
+  void* start = (w->timed < w->timing_slots() && !w->timing_started) ? w->timing[2 * w->timed] : nullptr;
+  const int rc = launch_beam(view_beam_params(w, f, w->d_view, out_dev), stream, start);
   if (rc == SVD_OK) w->beamed = out_dev;
+  if (rc == SVD_OK && start) w->timing_started = true;
   return rc;
 }
 
@@ -503,7 +507,48 @@ extern "C" int svd_view_trace(svd_world* w, const svd_ray_frame* f, svd_hit* out
     if (rc) return rc;
   }
   w->beamed = nullptr;
-  return launch_trace(tp, view_trace_blocks(w, tp), stream);
+  void *start = nullptr, *stop = nullptr;
+  if (w->timed < w->timing_slots()) {
+    if (!w->timing_started) start = w->timing[2 * w->timed];
+    stop = w->timing[2 * w->timed + 1];
+  }
+  const int rc = launch_trace(tp, view_trace_blocks(w, tp), stream, start, stop);
+  if (stop) {
+    if (rc == SVD_OK) w->timed++;
+    w->timing_started = false;
+  }
+  return rc;
+}
+
+extern "C" int svd_world_time_traces(svd_world* w, uint32_t n) {
+  if (!w) return svd_fail(SVD_EINVAL, "svd_world_time_traces: null world");
+  if (n > SVD_MAX_TIMED_PASSES)
+    return svd_fail(SVD_EINVAL, "time_traces: at most %u passes, asked for %u", (unsigned)SVD_MAX_TIMED_PASSES, n);
+  w->drop_timing();
+  w->timing.reserve(2 * (size_t)n);
+  for (uint32_t i = 0; i < 2 * n; i++) {
+    hipEvent_t e = nullptr;
+    const hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) {
+      w->drop_timing();
+      return svd_fail(SVD_EDEVICE, "time_traces: %s", hipGetErrorString(err));
+    }
+    w->timing.push_back(e);
+  }
+  return SVD_OK;
+}
+
+extern "C" int svd_world_trace_times(svd_world* w, float* ms, uint32_t n, uint32_t* count) {
+  if (!w || !count || (n && !ms)) return svd_fail(SVD_EINVAL, "svd_world_trace_times: null argument");
+  *count = 0;
+  const uint32_t m = std::min(n, w->timed);
+  for (uint32_t i = 0; i < m; i++) {
+    hipError_t err = hipEventSynchronize(w->timing[2 * i + 1]);
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms[i], w->timing[2 * i], w->timing[2 * i + 1]);
+    if (err != hipSuccess) return svd_fail(SVD_EDEVICE, "trace_times: pass %u: %s", i, hipGetErrorString(err));
+    *count = i + 1;
+  }
+  return SVD_OK;
 }
 
 extern "C" int svd_world_set_occupancy(svd_world* w, uint32_t blocks_per_cu) {

@@ -182,8 +182,10 @@ int check_frame(const svd_ray_frame* f);
 // kernels.hip
 int launch_chunk_stage(const StageParams& p, void* stream);
 uint32_t host_stage_chunk(const StageParams& p, uint32_t ci);  // the stage's decision, on the host
-int launch_trace(const TraceParams& p, uint32_t blocks, void* stream);
-int launch_beam(const BeamParams& p, void* stream);
+// `start` / `stop` (hipEvent_t, may be null): events that take their
+// timestamps from the kernel's own dispatch, not from marker commands
+int launch_trace(const TraceParams& p, uint32_t blocks, void* stream, void* start = nullptr, void* stop = nullptr);
+int launch_beam(const BeamParams& p, void* stream, void* start = nullptr);
 int trace_occupancy(uint32_t* blocks_per_cu);
 int launch_set_desc(DevDag* dst, const DevDag* src4, uint32_t n, void* stream);
 // batched views: queue reset, per-(view, chunk) stage, persistent trace
@@ -266,6 +268,21 @@ struct svd_world {
   bool has_staged = false;
   bool staged_beam = false;  // the trace of the staged view runs the beam pass
   const svd_hit* beamed = nullptr;  // output that already holds the staged view's tile bounds
+  // Timing of the next trace passes (svd_world_time_traces): a start and a
+  // stop event per armed pass, stamped by the kernels' own dispatches.
+  std::vector<hipEvent_t> timing;  // [2 * pass + 0/1]
+  uint32_t timed = 0;              // passes recorded so far
+  bool timing_started = false;     // the current pass's start was stamped by its beam launch
+
+  uint32_t timing_slots() const { return (uint32_t)(timing.size() / 2); }
+  void drop_timing() {
+    for (uint32_t i = 0; i < timed; i++) (void)hipEventSynchronize(timing[2 * i + 1]);
+    for (hipEvent_t e : timing) (void)hipEventDestroy(e);
+    timing.clear();
+    timed = 0;
+    timing_started = false;
+  }
+  ~svd_world() { drop_timing(); }
 
   bool alloc(size_t bytes, size_t* off) {
     bytes = (bytes + 255) / 256 * 256;

@@ -25,6 +25,7 @@ SVD_ENOTFOUND = -6
 SVD_EIO = -7
 SVD_NO_CULL = 1
 SVD_BEAM = 2
+SVD_MAX_TIMED_PASSES = 65536
 FAULT_CHUNK = 0xFFFFFFFE  # written by the trace if its chunk-walk iteration guard fires (never expected)
 CHUNK_NOT_LOADED = 0xFFFFFFFD  # a ray reached a chunk whose picked LOD is only described
 
@@ -45,6 +46,7 @@ EXPORTS = [
     "svd_server_stats_get", "svd_server_destroy", "svd_batch_trace_frames_static",
     "svd_world_set_tiling", "svd_world_get_tiling", "svd_world_tune", "svd_batch_tune_cached",
     "svd_kernel_hash", "svd_tune_cache_lookup", "svd_tune_cache_store",
+    "svd_world_time_traces", "svd_world_trace_times",
 ]
 
 
@@ -151,6 +153,8 @@ def lib() -> ctypes.CDLL:
         L.svd_view_stage.argtypes = [vp, ctypes.POINTER(svd_ray_frame), u32, vp]
         L.svd_view_trace.argtypes = [vp, ctypes.POINTER(svd_ray_frame), vp, vp]
         L.svd_view_beam.argtypes = [vp, ctypes.POINTER(svd_ray_frame), vp, vp]
+        L.svd_world_time_traces.argtypes = [vp, u32]
+        L.svd_world_trace_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), u32, ctypes.POINTER(u32)]
         L.svd_world_set_occupancy.argtypes = [vp, u32]
         L.svd_world_get_occupancy.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32)]
         u64 = ctypes.c_uint64
@@ -421,6 +425,18 @@ def svd_view_beam(w: World, frame: svd_ray_frame, out, stream=None):
 def svd_view_trace(w: World, frame: svd_ray_frame, out, stream=None):
     _check(lib().svd_view_trace(w.ptr, ctypes.byref(frame), _out_ptr(out, frame.width * frame.height),
                                 _stream_ptr(stream)))
+
+
+def svd_world_time_traces(w: World, n: int):
+    _check(lib().svd_world_time_traces(w.ptr, n))
+
+
+def svd_world_trace_times(w: World, n: int):
+    """Durations (ms) of the first min(n, recorded) timed trace passes."""
+    ms = (ctypes.c_float * max(1, n))()
+    count = ctypes.c_uint32()
+    _check(lib().svd_world_trace_times(w.ptr, ms, n, ctypes.byref(count)))
+    return [ms[i] for i in range(count.value)]
 
 
 def svd_world_set_occupancy(w: World, blocks_per_cu: int):

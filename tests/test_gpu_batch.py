@@ -249,3 +249,41 @@ def test_per_view_tilings_and_tuning_cache(env, world, tmp_path):
     finally:
         svdag.svd_world_set_tiling(w, 0)
         svdag.svd_world_set_occupancy(w, 0)
+
+
+def test_trace_pass_timing(env, world):
+    """Armed trace passes take their kernel time from the dispatches, with and
+    without the beam pass, and records do not change; passes beyond the armed
+    count run untimed, arming again drops earlier records, and a pass split
+    into stage, beam and trace calls is timed once."""
+    svdag, torch = env
+    sw, w, ow = world
+    cams = _cams(sw, 11, 5)
+    ref = _per_view(svdag, torch, w, cams)
+    try:
+        for flags in (0, svdag.SVD_BEAM):
+            note(f"timed passes, flags {flags}")
+            svdag.svd_world_time_traces(w, 3)
+            assert svdag.svd_world_trace_times(w, 3) == []
+            assert np.array_equal(_per_view_flags(svdag, torch, w, cams, flags), ref), flags  # 5 passes
+            ms = svdag.svd_world_trace_times(w, 8)
+            assert len(ms) == 3 and all(0.0 < m < 1000.0 for m in ms), ms
+            assert svdag.svd_world_trace_times(w, 2) == ms[:2]
+        c = cams[2]
+        n = c.width * c.height
+        start = sum(x.width * x.height for x in cams[:2])
+        f = svdag.svd_camera_frame(svdag.to_camera(c))
+        o = torch.full((n, 4), -1, dtype=torch.int32, device="cuda")
+        svdag.svd_world_time_traces(w, 1)
+        svdag.svd_view_stage(w, f, svdag.SVD_BEAM)
+        svdag.svd_view_beam(w, f, o)
+        svdag.svd_view_trace(w, f, o)
+        ms = svdag.svd_world_trace_times(w, 4)
+        assert len(ms) == 1 and ms[0] > 0.0, ms
+        assert np.array_equal(o.cpu().numpy(), ref[start:start + n])
+        with pytest.raises(svdag.SvdError) as e:
+            svdag.svd_world_time_traces(w, svdag.SVD_MAX_TIMED_PASSES + 1)
+        assert e.value.code == svdag.SVD_EINVAL
+    finally:
+        svdag.svd_world_time_traces(w, 0)
+    assert svdag.svd_world_trace_times(w, 4) == []
