@@ -22,7 +22,8 @@ Prints one JSON line (rank 0).  Besides the throughput it reports:
 Other workloads: --workload terrain1024 | noise64 | map1024.  map1024 (32x32
 chunks of 1024^3) is generated on the GPU with --gen gpu (the same bytes as
 the host generator) and runs with --no-cpu-baseline, since the oracle cannot
-build all of its chunks within the run.
+build all of its chunks within the run.  The default run also times the
+per-view leg of terrain1024 and noise64 (other_workloads; --other-workloads).
 """
 from __future__ import annotations
 
@@ -284,6 +285,9 @@ def main():
     ap.add_argument("--gen", choices=("host", "gpu"), default="host",
                     help="generate the scene's chunks on the host or with the GPU copy of the generator "
                          "(same bytes; gpu makes map1024 practical)")
+    ap.add_argument("--other-workloads", default="terrain1024,noise64",
+                    help="comma-separated workloads whose per-view leg also runs, without the oracle "
+                         "legs ('' = none)")
     ap.add_argument("--c4-seconds", type=float, default=32.0,
                     help="length of each served run on map1024 (0 = skip that leg)")
     ap.add_argument("--c4-rate", type=float, default=200.0, help="request arrival rate on map1024 (req/s)")
@@ -309,6 +313,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n, "launches": 3}))
         return
+    for name in (w for w in args.other_workloads.split(",") if w):
+        if name not in WORKLOADS:
+            ap.error(f"--other-workloads: unknown workload {name!r}")
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path does not "
               "shard across GPUs here (views would be routed to GPUs by chunk locality; there is no "
@@ -594,6 +601,12 @@ def main():
     blobs.clear()
     ow = None
     torch.cuda.empty_cache()
+    others = [w for w in args.other_workloads.split(",") if w and w != args.workload]
+    if others:
+        result["other_workloads"] = {}
+        for name in others:
+            result["other_workloads"][name] = bench_other_workload(args, name, svdag, torch, cache)
+            torch.cuda.empty_cache()
     if args.c4_seconds > 0 and args.workload != "map1024":
         # the served configuration: 32x32 chunks of 1024^3, pool at a quarter
         # of the map, Poisson arrivals at 200 requests/s from walkers
@@ -618,6 +631,54 @@ def main():
     result["bench_seconds"] = round(time.time() - t_begin, 1)
 
     print(json.dumps(result), flush=True)
+
+
+def bench_other_workload(args, name, svdag, torch, cache):
+    """The per-view leg alone on another workload (chunks generated on the
+    host, every LOD resident; tile and occupancy tuned or from the cache):
+    the same timed steps as the headline, without the oracle legs."""
+    from paper_2505_02017_amd import scenes
+    t0 = time.time()
+    kind, lod_count, thr, wdesc = WORKLOADS[name]
+    sw = scenes.SceneWorld(kind, args.seed)
+    cams = sw.views(args.views, 1)
+    W, H = cams[0].width, cams[0].height
+    blobs = build_chunks(args, sw, lod_count, "host", svdag, torch)
+    world, pool, _ = make_world(sw, blobs, lod_count, thr, svdag, torch)
+    frames = [svdag.svd_camera_frame(c) for c in cams]
+    out = torch.empty((W * H, 4), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    tuned, _ = tune_world(svdag, world, frames, out, 0, cache, stream)
+
+    def step(i):
+        f = frames[i % len(frames)]
+        svdag.svd_view_stage(world, f, 0, stream)
+        svdag.svd_view_trace(world, f, out, stream)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    svdag.svd_world_time_traces(world, args.steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    trace_ms = np.array(svdag.svd_world_trace_times(world, args.steps), dtype=np.float64)
+    svdag.svd_world_time_traces(world, 0)
+    hits = svdag.decode_hits(out.cpu().numpy())
+    assert not np.any(hits["chunk"] == svdag.FAULT_CHUNK), "iteration guard fired"
+    r = {"workload": wdesc, "value": round(W * H * args.steps / dt / 1e9, 4), "unit": "Grays/s",
+         "steps": args.steps, "ms_per_step": round(dt * 1e3 / args.steps, 4),
+         "trace_kernel_ms_mean": round(float(trace_ms.mean()), 4),
+         "tile": f"{tuned.tile_w}x{64 // tuned.tile_w}", "blocks_per_cu": tuned.blocks_per_cu,
+         "tuning_from_cache": bool(tuned.from_cache), "hit_fraction": round(float(hits["hit"].mean()), 4),
+         "seconds": round(time.time() - t0, 1)}
+    log(f"{name}: {r['value']} Grays/s, trace {r['trace_kernel_ms_mean']} ms, tile {r['tile']}, "
+        f"{r['blocks_per_cu']} blocks/CU")
+    del world, pool
+    return r
 
 
 def bench_batched(args, sw, world, svdag, torch, cache):

@@ -17,6 +17,13 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
+def test_unknown_other_workload_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--other-workloads", "terrain1024,nope"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "unknown workload 'nope'" in r.stderr and r.stdout == ""
+
+
 def _counts_and_hits():
     cnt = np.zeros(3, dtype=[("chunk_visits", np.int32), ("chunk_entries", np.int32),
                              ("node_cubes", np.int32), ("leaf_cubes", np.int32),
