@@ -303,6 +303,16 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
   // Chunk walk: c and E describe the current chunk (level CL).
   while (status == kRunning) {
     if (++iter > kMaxIter) { status = kFault; break; }
+#ifdef __HIP_DEVICE_COMPILE__
+    // Issue priority of the wave: rays that keep crossing chunks are the long
+    // ones (far, grazing rays), and their tiles are the launch's critical
+    // path.  The wave raises its priority as a ray reaches its 2nd, 4th and
+    // 8th chunk, so the SIMD's arbiter issues its instructions ahead of waves
+    // whose rays ended nearby (scheduling only; the tile loop resets it).
+    if (iter == 2) __builtin_amdgcn_s_setprio(1);
+    if (iter == 4) __builtin_amdgcn_s_setprio(2);
+    if (iter == 8) __builtin_amdgcn_s_setprio(3);
+#endif
     SVD_WALK_EVENT(chunk_visit);
     if (c[0] >= (int32_t)p.grid[0] || c[1] >= (int32_t)p.grid[1] || c[2] >= (int32_t)p.grid[2]) {
       status = kMiss;  // left the world
@@ -566,6 +576,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 6))) 
       }
       break;
     }
+    __builtin_amdgcn_s_setprio(0);  // a new tile starts at the lowest priority
     const uint32_t x0 = (t % p.tiles_x) * tw, y0 = (t / p.tiles_x) * th;
     const uint32_t px = x0 + (lane & (tw - 1)), py = y0 + (lane >> tw_log2);
     uint4* out = reinterpret_cast<uint4*>(p.out);
@@ -894,6 +905,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 6))) 
     uint32_t t0 = 0, t1 = 0;
     if (!take_tiles(p.queue, total, claim, home, lane, qi, t0, t1)) break;
     for (uint32_t t = t0; t < t1; t++) {
+      __builtin_amdgcn_s_setprio(0);  // a new tile starts at the lowest priority
       uint32_t lo = 0, hi = nviews;  // view holding global tile t
       while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
