@@ -175,6 +175,15 @@ struct Ray {
   }
 };
 
+// Bit i of m (i < 32): one bit-field extract on the GPU.
+__host__ __device__ __forceinline__ uint32_t bit_at(uint32_t m, uint32_t i) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return __builtin_amdgcn_ubfe(m, i, 1);
+#else
+  return (m >> i) & 1u;
+#endif
+}
+
 // Leave the current cell (any level; E its exit-plane numerators): the
 // earliest exit plane sets the ray's new instant.  `step` gets the axes that
 // step (bit a; every axis that ties).  False when D == 0: the ray never
@@ -364,7 +373,7 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
       // level, so the walk inside a chunk ends whatever the DAG holds.
       for (;;) {
         SVD_WALK_EVENT(iter);
-        uint32_t full = (mask >> oct) & 1u;
+        uint32_t full = bit_at(mask, oct);
         // A non-empty cell at the LOD's level (the walk never goes below
         // level k, so lev <= k means lev == k) is the hit.  The loop leaves
         // without setting the status: the hit is the one exit with the
@@ -404,7 +413,7 @@ __host__ __device__ inline uint4 trace_pixel(const TraceParams& p, uint32_t px, 
               c[a] = n;
             }
             const int pl = lev + (32 - __builtin_clz(diff));
-            const int nl = pl > CL ? CL : pl - 1;
+            const int nl = min(pl - 1, CL);
             _Pragma("unroll") for (int a = 0; a < 3; a++) {
               c[a] >>= (nl - lev);
               E[a] = ((uint32_t)(c[a] + 1) << (nl + 16)) - r.Oml[a];
