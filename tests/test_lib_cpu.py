@@ -33,6 +33,19 @@ def test_exports_match_header():
     assert declared == set(svdag.EXPORTS)
 
 
+def test_header_constants_match_binding():
+    """Every numeric #define of the C header has the same value in the binding."""
+    svdag = _svdag()
+    hdr = open(os.path.join(ROOT, "include", "svdag.h")).read()
+    consts = re.findall(r"^#define\s+(SVD_[A-Z0-9_]+)\s+\(?(-?(?:0x[0-9A-Fa-f]+|\d+))u?\)?", hdr, re.M)
+    assert len(consts) >= 12
+    for name, val in consts:
+        if hasattr(svdag, name):
+            assert getattr(svdag, name) == int(val, 0), name
+    for name in ("SVD_OK", "SVD_EINVAL", "SVD_EIO", "SVD_NO_CULL", "SVD_BEAM", "SVD_MAX_TIMED_PASSES"):
+        assert hasattr(svdag, name), name
+
+
 def _compare_blob(svdag, g, R, lod_count):
     b = svdag.svd_chunk_build(g, R.bit_length() - 1, lod_count)
     pyr = oracle.pyramid(g, R, lod_count)
