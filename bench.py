@@ -542,6 +542,15 @@ def main():
                                     "insts_per_launch": int(float(prof["valu_insts_per_launch"]))}
             if "valu_lane_utilisation" in prof:
                 result["valu_issue"]["lane_utilisation"] = float(prof["valu_lane_utilisation"])
+            if "shader_clock_ghz" in prof:
+                # the same issue rate against the clock the chip ran the
+                # kernel at, and the share of the launch its CUs were busy
+                # (SQ / GRBM cycle counters of the same kernel source)
+                clk = float(prof["shader_clock_ghz"])
+                result["valu_issue"]["shader_clock_ghz"] = clk
+                result["valu_issue"]["frac_at_measured_clock"] = round(rate / (1024 * clk * 1e9 / 4), 4)
+                if "cu_busy_fraction" in prof:
+                    result["valu_issue"]["cu_busy_fraction"] = float(prof["cu_busy_fraction"])
             # the unit that binds: VALU issue, not HBM
             result["roofline"]["limiter"] = {"unit": "valu_issue", "frac": round(rate / peak, 4)}
         # ---- CPU baseline: the oracle (as is) on a bounded sample: whole views
